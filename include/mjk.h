@@ -1,0 +1,181 @@
+/*
+ * mjk.h -- C ABI of the MI355X (gfx950) library that evaluates two-electron
+ * repulsion integrals (ERIs) over contracted Cartesian Gaussian shells and
+ * contracts them at once with a density matrix into the Coulomb (J) and
+ * exchange (K) matrices.
+ *
+ * Problem statement (arXiv 2412.13203, Sections 2.1-2.2):
+ *   - a contracted basis function is a fixed linear combination of primitive
+ *     Cartesian Gaussians sharing one angular momentum (Eq. 1);
+ *   - a contracted ERI (ab|cd) is the sum over primitive quartets of the
+ *     coefficient products times the primitive integrals (Eq. 2), evaluated
+ *     by horizontal and vertical recurrences down to an analytic [00|00];
+ *   - the SCF loop builds the two-electron part of the Fock matrix from the
+ *     current density at every iteration (Section 2.1):
+ *         J_mn = sum_ls (mn|ls) D_ls,   K_mn = sum_ls (ml|ns) D_ls.
+ *
+ * Conventions shared by every call:
+ *   - Units are bohr.  Real Cartesian functions, chemists' notation.
+ *   - Shells: l in 0..3, 1..6 primitives.  Coefficients are final: they
+ *     multiply the unnormalized primitive x^i y^j z^k exp(-alpha r^2); the
+ *     library never normalizes.
+ *   - AO order: shells in input order; inside a shell the Cartesian
+ *     components are lexicographic (d: xx xy xz yy yz zz; f: xxx xxy xxz xyy
+ *     xyz xzz yyy yyz yzz zzz).  Matrices are nbf x nbf row-major float64.
+ *   - Device pointers (D, J, K, out, workspace) are caller-owned memory on
+ *     the context's device, e.g. contiguous torch tensors.  Host pointers are
+ *     read during the call only (basis arrays: during mjk_plan_create).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work calls are asynchronous on it unless stated otherwise.
+ *   - Every function returns an int status: MJK_OK (0) or a negative error
+ *     code; mjk_last_error() gives the message of the last failure on the
+ *     calling thread.  No exception crosses the ABI.  Arguments are checked
+ *     on the host before any launch; a device fault surfaces at the next call
+ *     that synchronizes.
+ */
+#ifndef MJK_H
+#define MJK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MJK_OK 0
+#define MJK_ERR_INVALID_ARG (-1)  /* null pointer, bad index, bad size, non-finite input  */
+#define MJK_ERR_UNSUPPORTED (-2)  /* l > lmax of the build, nprim outside 1..6            */
+#define MJK_ERR_NO_DEVICE (-3)    /* no HIP device, or not a gfx950 device                */
+#define MJK_ERR_WORKSPACE (-4)    /* workspace pointer null, misaligned or too small      */
+#define MJK_ERR_HIP (-5)          /* a HIP runtime call failed                            */
+#define MJK_ERR_STATE (-6)        /* call out of order (e.g. build before bind)           */
+
+/* Flags of mjk_jk_opts.flags */
+#define MJK_FLAG_CHECK 0x1u       /* check D on the host side of the call: finite and symmetric */
+
+typedef struct mjk_ctx mjk_ctx;
+typedef struct mjk_plan mjk_plan;
+
+/* Contracted basis on atoms (host memory, read by mjk_plan_create only).
+ * Eq. 1: shell s is sum_k coefs[prim_off+k] * primitive(exps[prim_off+k]),
+ * k < shell_nprim[s], centred on atom shell_atom[s]. */
+typedef struct mjk_basis {
+    int32_t natom;
+    const double *xyz;            /* natom x 3, bohr                         */
+    int32_t nshell;
+    const int32_t *shell_atom;    /* nshell, 0..natom-1                      */
+    const int32_t *shell_l;       /* nshell, 0..3                            */
+    const int32_t *shell_nprim;   /* nshell, 1..6                            */
+    const int32_t *shell_prim_off;/* nshell, offset into exps / coefs        */
+    int64_t nprim;                /* length of exps and coefs                */
+    const double *exps;           /* > 0, finite                             */
+    const double *coefs;          /* finite                                  */
+} mjk_basis;
+
+/* Options of a plan.
+ * schwarz_tau: a unique shell quartet (AB|CD) is skipped iff
+ *   Q_AB * Q_CD < schwarz_tau, with Q_AB = sqrt(max_{a in A, b in B} (ab|ab))
+ *   (Cauchy-Schwarz bound; 0 keeps every quartet).
+ * fp32_tau: reserved for the mixed-precision form; must be 0 here. */
+typedef struct mjk_jk_opts {
+    double schwarz_tau;
+    double fp32_tau;
+    uint32_t flags;
+} mjk_jk_opts;
+
+/* Plan statistics (filled after mjk_plan_bind). */
+typedef struct mjk_plan_stats {
+    int64_t nbf;
+    int64_t nshell;
+    int64_t npair;              /* shell pairs A >= B                              */
+    int64_t nprim_pair;         /* primitive pairs over all shell pairs            */
+    int64_t nquartet_total;     /* unique shell quartets before screening          */
+    int64_t nquartet_kept;      /* unique shell quartets after screening           */
+    int64_t nprim_quartet_kept; /* primitive quartets of the kept quartets         */
+    int64_t ncart_eri_kept;     /* Cartesian integrals of the kept quartets        */
+    int64_t nlaunch;            /* kernel launches per mjk_build_jk                */
+    double vrr_flops_kept;      /* algorithmic flops of the kept quartets          */
+    size_t workspace_bytes;
+} mjk_plan_stats;
+
+/* Library identification: lmax of the build (highest shell l supported). */
+int mjk_lmax(void);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *mjk_last_error(void);
+
+/* Context on HIP device `device` (must be gfx950).  Returns MJK_ERR_NO_DEVICE
+ * when no such device exists. */
+int mjk_ctx_create(int device, mjk_ctx **out);
+void mjk_ctx_destroy(mjk_ctx *ctx);
+
+/* Number of Cartesian basis functions of `basis` (host-only, no device). */
+int mjk_nbf(const mjk_basis *basis, int64_t *nbf);
+
+/* Validate the basis and options, copy them, and report the device
+ * workspace the plan needs (bytes, 256-byte aligned start required).
+ * Host-only: no device memory is touched. */
+int mjk_plan_create(mjk_ctx *ctx, const mjk_basis *basis, const mjk_jk_opts *opts, mjk_plan **out,
+                    size_t *workspace_bytes);
+
+/* Bind the caller's device workspace and build the tables in it, on
+ * `stream`: shell-pair and primitive-pair tables, Schwarz factors, the
+ * class-sorted pair order and the quartet work lists (Section 5: pairs
+ * sorted by angular momentum and tiled within a class; quartet blocks are
+ * formed from pair tiles).  Synchronizes `stream` once (the Schwarz factors
+ * come back to the host for the sort).  The workspace must stay allocated
+ * and untouched until mjk_plan_destroy or the next bind. */
+int mjk_plan_bind(mjk_plan *plan, void *workspace, size_t bytes, void *stream);
+
+/* J and K for density D (nbf x nbf, symmetric), both overwritten.
+ * D, J, K: device float64, row-major, distinct buffers.  Asynchronous on
+ * `stream`.  With MJK_FLAG_CHECK in the plan's flags, D is copied to the
+ * host and checked first (finite, symmetric to 1e-12 max|D|). */
+int mjk_build_jk(mjk_plan *plan, const double *D, double *J, double *K, void *stream);
+
+/* Explicit contracted ERI blocks (Eq. 2) for nq shell quartets.
+ * quartets: host int32, nq x 4 shell indices (A, B, C, D) in any order.
+ * out: device float64; quartet q occupies na*nb*nc*nd values, row-major over
+ * (a, b, c, d) in the caller's shell order, blocks back to back in request
+ * order; out_len must equal the total.  No screening is applied. */
+int mjk_eri_class(mjk_plan *plan, const int32_t *quartets, int64_t nq, double *out, int64_t out_len,
+                  void *stream);
+
+/* Schwarz factors Q[A][B] (host float64, nshell x nshell, symmetric) as
+ * used by the plan.  Synchronous. */
+int mjk_schwarz(mjk_plan *plan, double *Q_host);
+
+/* Plan statistics (host, synchronous, no device work). */
+int mjk_plan_stats_get(const mjk_plan *plan, mjk_plan_stats *stats);
+
+/* Per-class kernel timing, for measurement tools.  With timing enabled,
+ * mjk_build_jk records a HIP event pair on `stream` around every class
+ * launch.  After that stream has completed, mjk_plan_timings sums, per
+ * quartet class (la lb | lc ld), the milliseconds and launches of the last
+ * mjk_build_jk, and the algorithmic work they covered: primitive quartets,
+ * shell quartets and floating-point operations (per primitive quartet:
+ * geometry, Boys function, vertical recurrence and accumulation; per shell
+ * quartet: horizontal recurrence and digestion, 12 flops per integral).
+ * out: host array of cap records; *n receives the number of classes with
+ * work (at most cap are written).  Synchronizes nothing itself; returns
+ * MJK_ERR_STATE if timing was off during the last build. */
+typedef struct mjk_class_timing {
+    int32_t la, lb, lc, ld;
+    int32_t nlaunch;
+    double ms;
+    int64_t nquartet;
+    int64_t nprim_quartet;
+    double flops;
+} mjk_class_timing;
+
+int mjk_plan_set_timing(mjk_plan *plan, int enable);
+int mjk_plan_timings(mjk_plan *plan, mjk_class_timing *out, int32_t cap, int32_t *n);
+
+void mjk_plan_destroy(mjk_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MJK_H */

@@ -1,0 +1,96 @@
+"""Build the gfx950 library: generate the per-class sources, compile, link.
+
+    python -m paper_2412_13203_amd.build [--jobs N] [--lmax L]
+
+Produces paper_2412_13203_amd/_lib/libmjk.so (in-tree; loaded by the
+Python binding).  Every call regenerates and recompiles.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import os
+import shutil
+import subprocess
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+GEN = os.path.join(CSRC, "gen")
+LIBDIR = os.path.join(HERE, "_lib")
+OBJDIR = os.path.join(HERE, "_lib", "obj")
+LIB = os.path.join(LIBDIR, "libmjk.so")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+HIP_FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
+    # packed FP32 (v_pk_*_f32) generation off
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-result", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+]
+
+
+def generate(lmax: int = 2):
+    sys.path.insert(0, os.path.join(HERE, "gen"))
+    try:
+        import boys_gen
+        import eri_gen
+    finally:
+        sys.path.pop(0)
+    if os.path.isdir(GEN):
+        for f in glob.glob(os.path.join(GEN, "tu_*.hip")):
+            os.remove(f)
+    boys_gen.generate(GEN)
+    _, tus = eri_gen.generate(GEN, lmax)
+    return tus
+
+
+def _compile(src, verbose):
+    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    cmd = [HIPCC] + HIP_FLAGS + ["-c", "-x", "hip", src, "-o", obj]
+    t0 = time.time()
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {src}\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print(f"  {os.path.basename(src)}: {time.time() - t0:.1f}s", flush=True)
+    return obj
+
+
+def build(verbose: bool = True, jobs: int | None = None, lmax: int = 2) -> str:
+    t0 = time.time()
+    tus = generate(lmax)
+    if os.path.isdir(OBJDIR):
+        shutil.rmtree(OBJDIR)
+    os.makedirs(OBJDIR, exist_ok=True)
+    srcs = [os.path.join(CSRC, "mjk_host.cpp"), os.path.join(CSRC, "device_util.hip")] + sorted(tus)
+    # heaviest translation units first
+    srcs.sort(key=lambda s: -os.path.getsize(s) if "tu_" not in s else -_weight(s))
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB} in {time.time() - t0:.1f}s", flush=True)
+    return LIB
+
+
+def _weight(tu):
+    name = os.path.basename(tu)[3:-4]
+    return sum("spdf".index(c) for c in name) * 10 + len(name)
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--lmax", type=int, default=2)
+    args = ap.parse_args()
+    build(jobs=args.jobs, lmax=args.lmax)

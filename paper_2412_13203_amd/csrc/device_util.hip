@@ -1,0 +1,108 @@
+// device_util.hip -- the small non-class kernels: primitive-pair table,
+// fill and in-place symmetrization.
+#include <hip/hip_runtime.h>
+
+#include "mjk_types.hpp"
+
+namespace mjk {
+
+struct ShellArrays {
+    const double *xyz;       // natom x 3
+    const int32_t *atom;     // nshell
+    const int32_t *prim_off; // nshell
+    const int32_t *nprim;    // nshell
+    const double *exps;
+    const double *coefs;
+};
+
+// One primitive pair per thread: p, 1/(2p), P, P - A and the folded
+// prefactor K = sqrt(2) pi^{5/4} c_a c_b exp(-ab/p |AB|^2) / p  (Eq. 2's
+// coefficients and the Gaussian product of the two primitives).
+__global__ __launch_bounds__(256) void k_pair_table(const ShellPairD *__restrict__ pairs, int npair,
+                                                    ShellArrays sh, PrimPairD *__restrict__ out, int nprim_pair)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nprim_pair) return;
+    int lo = 0, hi = npair;  // pairs[lo].prim_off <= t < pairs[lo+1].prim_off
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pairs[mid].prim_off <= t)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const ShellPairD pr = pairs[lo];
+    const int local = t - pr.prim_off;
+    // nprim = K_A * K_B, A-major
+    const int KB = sh.nprim[pr.B];
+    const int i = local / KB, j = local % KB;
+    const int ia = sh.prim_off[pr.A] + i, jb = sh.prim_off[pr.B] + j;
+    const double al = sh.exps[ia], be = sh.exps[jb];
+    const double *A = sh.xyz + 3 * sh.atom[pr.A];
+    const double *B = sh.xyz + 3 * sh.atom[pr.B];
+    const double p = al + be;
+    const double ip = 1.0 / p;
+    PrimPairD o;
+    o.p = p;
+    o.oo2p = 0.5 * ip;
+    double ab2 = 0.0;
+    for (int x = 0; x < 3; ++x) {
+        const double Px = (al * A[x] + be * B[x]) * ip;
+        o.P[x] = Px;
+        o.PA[x] = Px - A[x];
+        ab2 += (A[x] - B[x]) * (A[x] - B[x]);
+    }
+    const double c0 = 0x1.7a8ed27904870p+2;  // sqrt(2) pi^(5/4) = 5.914967172795613
+    o.K = c0 * sh.coefs[ia] * sh.coefs[jb] * exp(-al * be * ip * ab2) * ip;
+    o.pad = 0.0;
+    out[t] = o;
+}
+
+__global__ __launch_bounds__(256) void k_fill(double *__restrict__ x, int64_t n, double v)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[t] = v;
+}
+
+// M <- M + M^T in place; the thread of (i, j), i < j, owns both elements.
+__global__ __launch_bounds__(256) void k_symmetrize(double *__restrict__ M, int n)
+{
+    const int j = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (i >= n || j >= n || i > j) return;
+    if (i == j) {
+        M[(size_t)i * n + i] *= 2.0;
+    } else {
+        const double s = M[(size_t)i * n + j] + M[(size_t)j * n + i];
+        M[(size_t)i * n + j] = s;
+        M[(size_t)j * n + i] = s;
+    }
+}
+
+int launch_pair_table(const ShellPairD *pairs, int npair, const double *xyz, const int32_t *atom,
+                      const int32_t *prim_off, const int32_t *nprim, const double *exps, const double *coefs,
+                      PrimPairD *out, int nprim_pair, hipStream_t s)
+{
+    if (nprim_pair <= 0) return 0;
+    ShellArrays sh{xyz, atom, prim_off, nprim, exps, coefs};
+    hipLaunchKernelGGL(k_pair_table, dim3((nprim_pair + 255) / 256), dim3(256), 0, s, pairs, npair, sh, out,
+                       nprim_pair);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_fill(double *x, int64_t n, double v, hipStream_t s)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, v);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_symmetrize(double *M, int n, hipStream_t s)
+{
+    if (n <= 0) return 0;
+    const unsigned g = (unsigned)((n + 15) / 16);
+    hipLaunchKernelGGL(k_symmetrize, dim3(g, g), dim3(256), 0, s, M, n);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace mjk

@@ -1,0 +1,373 @@
+// kernels.hpp -- class-templated ERI kernels for gfx950 (wave64).
+//
+// Per primitive quartet (Eq. 2's summand) the device builds the geometry of
+// the Obara-Saika recurrence, the Boys function F_m(T) for m <= L, the base
+// integrals [00|00]^(m) = prefactor * F_m(T), and runs the generated vertical
+// recurrence, accumulating [e0|f0] over the primitive quartets of the shell
+// quartet (the contraction of Eq. 2).  The generated horizontal recurrence
+// then gives the Cartesian block (ab|cd), which the J/K kernel digests at
+// once into J and K (Section 7: the compute-bound ERIs fused with their
+// memory-bound neighbour, reduced with atomics).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mjk_types.hpp"
+
+namespace mjk {
+
+template <typename T>
+struct VrrGeom {
+    T PA[3], WP[3], QC[3], WQ[3];
+    T oo2p, oo2q, oo2pq, rho_p, rho_q;
+};
+
+template <int LA, int LB, int LC, int LD>
+struct EriClass;
+
+}  // namespace mjk
+
+#include "gen/boys_table.inc"
+
+namespace mjk {
+#include "gen/eri_classes.inc"
+
+__host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+
+// ---------------------------------------------------------------------------
+// Boys function F_m(T), m = 0..L (Section 2.2's analytic [00|00] needs it).
+// T < TMAX: Taylor expansion of F_L and exp(-T) about the nearest grid point
+// of a build-time table, then downward recursion
+//     F_m = (2T F_{m+1} + exp(-T)) / (2m + 1).
+// T >= TMAX: F_0 = sqrt(pi/T)/2 (erfc(sqrt T) < 1e-18 there) and the upward
+// recursion F_{m+1} = ((2m+1) F_m - exp(-T)) / (2T), stable for T >> m.
+// ---------------------------------------------------------------------------
+template <int L>
+__device__ __forceinline__ void boys_fm(double T, double *F)
+{
+    static_assert(L <= MJK_BOYS_LMAX, "Boys table too short for this class");
+    constexpr int K = MJK_BOYS_KTAY;
+    if (T < (double)MJK_BOYS_TMAX) {
+        const int i = (int)(T * (double)MJK_BOYS_DT_INV + 0.5);
+        const double md = (double)i * (1.0 / MJK_BOYS_DT_INV) - T;  // -(T - T0), |md| <= 1/32
+        const double *row = mjk_boys_table + i * MJK_BOYS_NCOL;
+        double f = row[L + K - 1];
+        double e = 1.0;
+#pragma unroll
+        for (int k = K - 1; k >= 1; --k) {
+            const double s = md * (1.0 / (double)k);
+            f = row[L + k - 1] + f * s;
+            e = 1.0 + e * s;
+        }
+        const double eT = row[MJK_BOYS_NCOL - 1] * e;
+        F[L] = f;
+        const double T2 = 2.0 * T;
+#pragma unroll
+        for (int m = L - 1; m >= 0; --m) F[m] = (T2 * F[m + 1] + eT) * (1.0 / (double)(2 * m + 1));
+    } else {
+        const double rT = 1.0 / T;
+        const double eT = exp(-T);
+        F[0] = 0.5 * sqrt(3.14159265358979323846 * rT);
+        const double h = 0.5 * rT;
+#pragma unroll
+        for (int m = 0; m < L; ++m) F[m + 1] = ((double)(2 * m + 1) * F[m] - eT) * h;
+    }
+}
+
+// Geometry of one primitive quartet, Obara-Saika notation:
+// rho = pq/(p+q), W = (pP + qQ)/(p+q), WP = W - P = -q/(p+q) PQ,
+// WQ = W - Q = p/(p+q) PQ, T = rho |PQ|^2, prefactor K_bra K_ket / sqrt(p+q).
+__device__ __forceinline__ double prim_geom(const PrimPairD &b, const PrimPairD &k, VrrGeom<double> &g,
+                                            double &T)
+{
+    const double PQx = b.P[0] - k.P[0], PQy = b.P[1] - k.P[1], PQz = b.P[2] - k.P[2];
+    const double r = rsqrt(b.p + k.p);
+    const double ipq = r * r;
+    const double rho_p = k.p * ipq, rho_q = b.p * ipq;
+    const double rho = b.p * rho_p;
+    T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+    g.PA[0] = b.PA[0];
+    g.PA[1] = b.PA[1];
+    g.PA[2] = b.PA[2];
+    g.QC[0] = k.PA[0];
+    g.QC[1] = k.PA[1];
+    g.QC[2] = k.PA[2];
+    g.WP[0] = -rho_p * PQx;
+    g.WP[1] = -rho_p * PQy;
+    g.WP[2] = -rho_p * PQz;
+    g.WQ[0] = rho_q * PQx;
+    g.WQ[1] = rho_q * PQy;
+    g.WQ[2] = rho_q * PQz;
+    g.oo2p = b.oo2p;
+    g.oo2q = k.oo2p;
+    g.oo2pq = 0.5 * ipq;
+    g.rho_p = rho_p;
+    g.rho_q = rho_q;
+    return b.K * k.K * r;
+}
+
+__device__ __forceinline__ PrimPairD load_prim(const PrimPairD *__restrict__ p)
+{
+    return *p;
+}
+
+// Contracted [e0|f0] of one shell quartet: loop over its primitive quartets.
+template <int LA, int LB, int LC, int LD>
+__device__ __forceinline__ void contract_quartet(const ShellPairD &bra, const ShellPairD &ket,
+                                                 const PrimPairD *__restrict__ prims, bool active,
+                                                 double *acc)
+{
+    using C = EriClass<LA, LB, LC, LD>;
+    constexpr int L = LA + LB + LC + LD;
+#pragma unroll
+    for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
+    const int nk = active ? ket.nprim : 0;
+    for (int ib = 0; ib < bra.nprim; ++ib) {
+        const PrimPairD bp = load_prim(prims + bra.prim_off + ib);
+        for (int ik = 0; ik < nk; ++ik) {
+            const PrimPairD kp = load_prim(prims + ket.prim_off + ik);
+            VrrGeom<double> g;
+            double T;
+            const double pref = prim_geom(bp, kp, g, T);
+            double F[L + 1];
+            boys_fm<L>(T, F);
+#pragma unroll
+            for (int m = 0; m <= L; ++m) F[m] *= pref;
+            C::template vrr<double>(F, g, acc);
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Fused J/K: one wave = one bra pair (uniform) x up to 64 ket pairs per
+// round (one per lane).  Digestion of (ab|cd) with the 8-fold symmetry of a
+// unique quartet, weight w = 1/(s_AB s_CD s_ABCD):
+//   Jt_ab += 2w D_cd   Jt_cd += 2w D_ab
+//   Kt_ac += w D_bd    Kt_ad += w D_bc    Kt_bc += w D_ad    Kt_bd += w D_ac
+// J = Jt + Jt^T and K = Kt + Kt^T afterwards (k_symmetrize).  Jt_ab is
+// bra-uniform, so it is reduced across the wave before its atomic.
+// ---------------------------------------------------------------------------
+template <int LA, int LB, int LC, int LD>
+__global__ __launch_bounds__(64) void k_jk(JKLaunch a)
+{
+    using C = EriClass<LA, LB, LC, LD>;
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    const int item = blockIdx.x;
+    const int lane = threadIdx.x;
+    // bra of this item: chunk_prefix[b] <= item < chunk_prefix[b + 1]
+    int lo = 0, hi = a.nbra;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.chunk_prefix[mid] <= item)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const int b = lo;
+    const int kbeg = (item - a.chunk_prefix[b]) * a.chunk;
+    const int kend = min(kbeg + a.chunk, a.ket_count[b]);
+    const int bra_pos = a.bra_begin + b;
+    const ShellPairD bra = a.pairs[bra_pos];
+    const int N = a.nbf;
+    const double *__restrict__ D = a.D;
+
+    double Dab[NA * NB];
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) Dab[i * NB + j] = D[(size_t)(bra.ao_a + i) * N + bra.ao_b + j];
+    double jab[NA * NB];
+#pragma unroll
+    for (int i = 0; i < NA * NB; ++i) jab[i] = 0.0;
+
+    for (int k0 = kbeg; k0 < kend; k0 += 64) {
+        const int k = k0 + lane;
+        const bool active = k < kend;
+        const int ket_pos = a.ket_begin + (active ? k : kbeg);
+        const ShellPairD ket = a.pairs[ket_pos];
+        double acc[C::NACC];
+        contract_quartet<LA, LB, LC, LD>(bra, ket, a.prims, active, acc);
+        double eri[C::NOUT];
+        C::template hrr<double>(acc, bra.AB, ket.AB, eri);
+
+        double s = 1.0;
+        if (bra.same) s *= 2.0;
+        if (ket.same) s *= 2.0;
+        if (a.same_bin && ket_pos == bra_pos) s *= 2.0;
+        const double w = active ? 1.0 / s : 0.0;
+
+        double Dcd[NC * ND];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int d = 0; d < ND; ++d) Dcd[c * ND + d] = D[(size_t)(ket.ao_a + c) * N + ket.ao_b + d];
+        // Jt_ab (wave-reduced later) and Jt_cd
+#pragma unroll
+        for (int ab = 0; ab < NA * NB; ++ab) {
+            double t = 0.0;
+#pragma unroll
+            for (int cd = 0; cd < NC * ND; ++cd) t += eri[ab * NC * ND + cd] * Dcd[cd];
+            jab[ab] += 2.0 * w * t;
+        }
+        if (active) {
+#pragma unroll
+            for (int cd = 0; cd < NC * ND; ++cd) {
+                double t = 0.0;
+#pragma unroll
+                for (int ab = 0; ab < NA * NB; ++ab) t += eri[ab * NC * ND + cd] * Dab[ab];
+                const int c = cd / ND, d = cd % ND;
+                atomicAdd(a.J + (size_t)(ket.ao_a + c) * N + ket.ao_b + d, 2.0 * w * t);
+            }
+            // Kt_ac += w sum_{b,d} (ab|cd) D_bd ; Kt_ad += w sum_{b,c} (ab|cd) D_bc
+#pragma unroll
+            for (int ia = 0; ia < NA; ++ia) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+                        for (int d = 0; d < ND; ++d)
+                            t += eri[((ia * NB + jb) * NC + c) * ND + d] *
+                                 D[(size_t)(bra.ao_b + jb) * N + ket.ao_b + d];
+                    atomicAdd(a.K + (size_t)(bra.ao_a + ia) * N + ket.ao_a + c, w * t);
+                }
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            t += eri[((ia * NB + jb) * NC + c) * ND + d] *
+                                 D[(size_t)(bra.ao_b + jb) * N + ket.ao_a + c];
+                    atomicAdd(a.K + (size_t)(bra.ao_a + ia) * N + ket.ao_b + d, w * t);
+                }
+            }
+            // Kt_bc += w sum_{a,d} (ab|cd) D_ad ; Kt_bd += w sum_{a,c} (ab|cd) D_ac
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                        for (int d = 0; d < ND; ++d)
+                            t += eri[((ia * NB + jb) * NC + c) * ND + d] *
+                                 D[(size_t)(bra.ao_a + ia) * N + ket.ao_b + d];
+                    atomicAdd(a.K + (size_t)(bra.ao_b + jb) * N + ket.ao_a + c, w * t);
+                }
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            t += eri[((ia * NB + jb) * NC + c) * ND + d] *
+                                 D[(size_t)(bra.ao_a + ia) * N + ket.ao_a + c];
+                    atomicAdd(a.K + (size_t)(bra.ao_b + jb) * N + ket.ao_b + d, w * t);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int ab = 0; ab < NA * NB; ++ab) {
+        const double t = wave_sum(jab[ab]);
+        if (lane == 0) atomicAdd(a.J + (size_t)(bra.ao_a + ab / NB) * N + bra.ao_b + ab % NB, t);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Explicit ERI blocks: one requested quartet per lane, canonical class order,
+// written back in the caller's shell order.
+// ---------------------------------------------------------------------------
+template <int LA, int LB, int LC, int LD>
+__global__ __launch_bounds__(64) void k_eri(EriLaunch a)
+{
+    using C = EriClass<LA, LB, LC, LD>;
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    const int t = blockIdx.x * 64 + threadIdx.x;
+    if (t >= a.n) return;
+    const EriItem it = a.items[t];
+    const ShellPairD bra = a.pairs[it.bra];
+    const ShellPairD ket = a.pairs[it.ket];
+    double acc[C::NACC];
+    contract_quartet<LA, LB, LC, LD>(bra, ket, a.prims, true, acc);
+    double eri[C::NOUT];
+    C::template hrr<double>(acc, bra.AB, ket.AB, eri);
+    const bool sab = it.flags & 1, scd = it.flags & 2, sbk = it.flags & 4;
+    double *out = a.out + it.out_off;
+    for (int i = 0; i < NA; ++i)
+        for (int j = 0; j < NB; ++j)
+            for (int k = 0; k < NC; ++k)
+                for (int l = 0; l < ND; ++l) {
+                    int x1, x2, x3, x4;
+                    if (!sbk) {
+                        x1 = sab ? j : i;
+                        x2 = sab ? i : j;
+                        x3 = scd ? l : k;
+                        x4 = scd ? k : l;
+                    } else {
+                        x1 = sab ? l : k;
+                        x2 = sab ? k : l;
+                        x3 = scd ? j : i;
+                        x4 = scd ? i : j;
+                    }
+                    out[((size_t)(x1 * it.n2 + x2) * it.n3 + x3) * it.n4 + x4] =
+                        eri[((i * NB + j) * NC + k) * ND + l];
+                }
+}
+
+// ---------------------------------------------------------------------------
+// Schwarz factors: Q_AB = sqrt(max_{a,b} (ab|ab)), one pair per lane.
+// ---------------------------------------------------------------------------
+template <int LA, int LB>
+__global__ __launch_bounds__(64) void k_schwarz(SchwarzLaunch a)
+{
+    using C = EriClass<LA, LB, LA, LB>;
+    constexpr int NA = ncart(LA), NB = ncart(LB);
+    const int t = blockIdx.x * 64 + threadIdx.x;
+    if (t >= a.n) return;
+    const int pi = a.idx[t];
+    const ShellPairD pr = a.pairs[pi];
+    double acc[C::NACC];
+    contract_quartet<LA, LB, LA, LB>(pr, pr, a.prims, true, acc);
+    double eri[C::NOUT];
+    C::template hrr<double>(acc, pr.AB, pr.AB, eri);
+    double mx = 0.0;
+#pragma unroll
+    for (int i = 0; i < NA * NB; ++i) mx = fmax(mx, eri[i * NA * NB + i]);
+    a.Q[pi] = sqrt(mx);
+}
+
+#define MJK_DEFINE_CLASS(LA, LB, LC, LD, NAME)                                                      \
+    int launch_jk_##NAME(const JKLaunch &a, hipStream_t s)                                         \
+    {                                                                                               \
+        if (a.nitems <= 0) return 0;                                                                \
+        hipLaunchKernelGGL((k_jk<LA, LB, LC, LD>), dim3(a.nitems), dim3(64), 0, s, a);              \
+        return hipGetLastError() == hipSuccess ? 0 : -1;                                            \
+    }                                                                                               \
+    int launch_eri_##NAME(const EriLaunch &a, hipStream_t s)                                       \
+    {                                                                                               \
+        if (a.n <= 0) return 0;                                                                     \
+        hipLaunchKernelGGL((k_eri<LA, LB, LC, LD>), dim3((a.n + 63) / 64), dim3(64), 0, s, a);      \
+        return hipGetLastError() == hipSuccess ? 0 : -1;                                            \
+    }
+
+#define MJK_DEFINE_SCHWARZ(LA, LB, NAME)                                                            \
+    int launch_schwarz_##NAME(const SchwarzLaunch &a, hipStream_t s)                               \
+    {                                                                                               \
+        if (a.n <= 0) return 0;                                                                     \
+        hipLaunchKernelGGL((k_schwarz<LA, LB>), dim3((a.n + 63) / 64), dim3(64), 0, s, a);          \
+        return hipGetLastError() == hipSuccess ? 0 : -1;                                            \
+    }
+
+}  // namespace mjk

@@ -1,0 +1,91 @@
+// mjk_types.hpp -- data laid out in device memory and the launch records
+// passed from the host planner to the class kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mjk {
+
+// One primitive pair (alpha on the first centre A, beta on the second B),
+// 80 bytes.  K folds the coefficients, the Gaussian product factor and the
+// pair part of the [00|00] prefactor:
+//   K = sqrt(2) pi^{5/4} c_a c_b exp(-alpha beta / p |AB|^2) / p,
+// so that K_bra K_ket / sqrt(p + q) = 2 pi^{5/2} / (p q sqrt(p+q)) * ...
+struct alignas(16) PrimPairD {
+    double p;        // alpha + beta
+    double oo2p;     // 1 / (2p)
+    double P[3];     // (alpha A + beta B) / p
+    double PA[3];    // P - A
+    double K;
+    double pad;
+};
+static_assert(sizeof(PrimPairD) == 80, "PrimPairD layout");
+
+// One shell pair, oriented so that l(A) >= l(B); 64 bytes.
+struct alignas(16) ShellPairD {
+    int32_t A, B;          // shell indices (first, second centre)
+    int32_t prim_off;      // first primitive pair in the primitive-pair table
+    int32_t nprim;         // K_A * K_B (A-major)
+    int32_t ao_a, ao_b;    // first AO index of A and of B
+    int32_t same;          // 1 if A == B (identical shells)
+    int32_t cls;           // pair class index la(la+1)/2 + lb
+    double AB[3];          // A - B
+    double Q;              // Schwarz factor
+};
+static_assert(sizeof(ShellPairD) == 64, "ShellPairD layout");
+
+// Explicit quartet for the eri_class path.
+struct alignas(16) EriItem {
+    int32_t bra, ket;      // pair indices in the natural pair table
+    int32_t flags;         // bit0: swap a<->b, bit1: swap c<->d, bit2: swap bra<->ket
+    int32_t pad;
+    int64_t out_off;       // first output element of this quartet
+    int32_t n1, n2, n3, n4;// caller's component counts (A, B, C, D)
+};
+
+struct JKLaunch {
+    const ShellPairD *pairs;   // class-sorted pair table
+    const PrimPairD *prims;
+    const double *D;
+    double *J;
+    double *K;
+    int32_t nbf;
+    int32_t bra_begin, nbra, ket_begin;
+    int32_t same_bin;          // bra and ket bins coincide: keep ket <= bra
+    const int32_t *ket_count;  // per bra: number of kets kept (a prefix of the bin)
+    const int32_t *chunk_prefix; // per bra: exclusive prefix of ket chunks (nbra + 1)
+    int32_t nitems;            // chunk_prefix[nbra]
+    int32_t chunk;             // kets per work item (multiple of 64)
+};
+
+struct EriLaunch {
+    const ShellPairD *pairs;   // natural pair table
+    const PrimPairD *prims;
+    const EriItem *items;
+    int32_t n;
+    double *out;
+};
+
+struct SchwarzLaunch {
+    const ShellPairD *pairs;   // natural pair table
+    const PrimPairD *prims;
+    const int32_t *idx;        // natural pair indices of one pair class
+    int32_t n;
+    double *Q;                 // natural order
+};
+
+using JKFn = int (*)(const JKLaunch &, hipStream_t);
+using EriFn = int (*)(const EriLaunch &, hipStream_t);
+using SchwarzFn = int (*)(const SchwarzLaunch &, hipStream_t);
+
+struct ClassEntry {
+    int la, lb, lc, ld;
+    int nacc, nout;
+    double vrr_flops;  // per primitive quartet
+    double hrr_flops;  // per contracted quartet
+    JKFn jk;
+    EriFn eri;
+    SchwarzFn schwarz;  // only on diagonal classes (la lb | la lb)
+};
+
+}  // namespace mjk

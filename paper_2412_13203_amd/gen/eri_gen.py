@@ -1,0 +1,532 @@
+"""Generator of the per-class ERI device code (run at build time).
+
+For a class (la lb | lc ld), la >= lb, lc >= ld, it emits straight-line HIP
+device functions templated on the arithmetic type T (double, float):
+
+  vrr_<cls>(F, geometry scalars, acc)  accumulate the primitive integrals
+      [e0|f0]^(0), |e| in [la, la+lb], |f| in [lc, lc+ld], into acc[]
+      (vertical recurrence of Obara and Saika; [00|00]^(m) = F[m], which the
+      caller has already multiplied by the quartet prefactor);
+  hrr_<cls>(acc, AB, CD, out)          horizontal recurrence of Head-Gordon
+      and Pople on the contracted values: (a,b+1_i| = (a+1_i,b| + AB_i (a,b|
+      on the bra and the same with CD on the ket; out[] is (ab|cd) row-major
+      over lexicographic Cartesian components.
+
+The split follows the paper's description of the recurrences (Section 2.2):
+HRR moves angular momentum from b to a (and d to c), VRR lowers it at a or c
+down to [00|00], which is evaluated analytically.  The contraction of Eq. 2
+happens between the two: the HRR coefficients AB, CD do not depend on the
+primitives.
+
+The order in which the recurrence lowers angular momentum is chosen by the
+greedy search of Section 6 (Algorithm 1): at each node, every candidate
+position (bra or ket centre, Cartesian direction) is scored by
+(new intermediates - reused intermediates) + lambda * (angular momentum left
+at that position), and the cheapest is taken.  The generator tries a few
+lambda values and keeps the path with the fewest floating-point operations.
+
+Recurrence used, with p, q the bra and ket exponent sums, rho = pq/(p+q),
+W = (pP + qQ)/(p+q):
+  [e+1_i|f]^(m) = PA_i [e|f]^(m) + WP_i [e|f]^(m+1)
+                  + e_i/(2p) ([e-1_i|f]^(m) - rho/p [e-1_i|f]^(m+1))
+                  + f_i/(2(p+q)) [e|f-1_i]^(m+1)
+  [e|f+1_i]^(m) = QC_i [e|f]^(m) + WQ_i [e|f]^(m+1)
+                  + f_i/(2q) ([e|f-1_i]^(m) - rho/q [e|f-1_i]^(m+1))
+                  + e_i/(2(p+q)) [e-1_i|f]^(m+1)
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+from dataclasses import dataclass, field
+
+AX = "xyz"
+
+
+def cart(l):
+    out = []
+    for i in range(l, -1, -1):
+        for j in range(l - i, -1, -1):
+            out.append((i, j, l - i - j))
+    return out
+
+
+def ncart(l):
+    return (l + 1) * (l + 2) // 2
+
+
+def cidx(t):
+    """Index of a Cartesian triple inside its shell (lexicographic)."""
+    return cart(sum(t)).index(tuple(t))
+
+
+def sub(t, i, k=1):
+    t = list(t)
+    t[i] -= k
+    return tuple(t)
+
+
+def add(t, i, k=1):
+    t = list(t)
+    t[i] += k
+    return tuple(t)
+
+
+ZERO3 = (0, 0, 0)
+
+
+# --------------------------------------------------------------------------
+# VRR DAG with the greedy path choice
+# --------------------------------------------------------------------------
+
+@dataclass
+class VNode:
+    e: tuple
+    f: tuple
+    m: int
+    side: str = ""        # 'b' (lower e) or 'k' (lower f) or '' for a base node
+    axis: int = -1
+    deps: dict = field(default_factory=dict)
+    name: str = ""
+
+
+class VRR:
+    def __init__(self, la, lb, lc, ld, lam):
+        self.la, self.lb, self.lc, self.ld = la, lb, lc, ld
+        self.L = la + lb + lc + ld
+        self.lam = lam
+        self.nodes = {}
+        self.order = []
+
+    def _children(self, e, f, m, side, i):
+        ch = {}
+        if side == "b":
+            e1 = sub(e, i)
+            ch["x1"] = (e1, f, m)
+            ch["x2"] = (e1, f, m + 1)
+            if e1[i] > 0:
+                e2 = sub(e1, i)
+                ch["x3"] = (e2, f, m)
+                ch["x4"] = (e2, f, m + 1)
+            if f[i] > 0:
+                ch["x5"] = (e1, sub(f, i), m + 1)
+        else:
+            f1 = sub(f, i)
+            ch["x1"] = (e, f1, m)
+            ch["x2"] = (e, f1, m + 1)
+            if f1[i] > 0:
+                f2 = sub(f1, i)
+                ch["x3"] = (e, f2, m)
+                ch["x4"] = (e, f2, m + 1)
+            if e[i] > 0:
+                ch["x5"] = (sub(e, i), f1, m + 1)
+        return ch
+
+    def need(self, e, f, m):
+        key = (e, f, m)
+        if key in self.nodes:
+            return self.nodes[key]
+        if e == ZERO3 and f == ZERO3:
+            node = VNode(e, f, m, name=f"F[{m}]")
+            self.nodes[key] = node
+            return node
+        # Algorithm 1: score every position, keep the cheapest
+        best = None
+        for side, t in (("b", e), ("k", f)):
+            for i in range(3):
+                if t[i] == 0:
+                    continue
+                ch = self._children(e, f, m, side, i)
+                r = sum(1 for c in ch.values() if c in self.nodes)
+                n = len(ch) - r
+                a = sum(t) - 1
+                cost = (n - r) + self.lam * a
+                # deterministic tie-break: prefer the bra, then x, y, z
+                tb = (cost, 0 if side == "b" else 1, i)
+                if best is None or tb < best[0]:
+                    best = (tb, side, i, ch)
+        _, side, i, ch = best
+        deps = {}
+        for k, c in ch.items():
+            deps[k] = self.need(*c)
+        node = VNode(e, f, m, side=side, axis=i, deps=deps)
+        node.name = f"v{len(self.order)}"
+        self.nodes[key] = node
+        self.order.append(node)
+        return node
+
+    def targets(self):
+        es = [t for l in range(self.la, self.la + self.lb + 1) for t in cart(l)]
+        fs = [t for l in range(self.lc, self.lc + self.ld + 1) for t in cart(l)]
+        return es, fs
+
+    def build(self):
+        es, fs = self.targets()
+        # highest angular momentum first: large nodes pull in shared low nodes
+        pairs = [(e, f) for e in es for f in fs]
+        pairs.sort(key=lambda ef: -(sum(ef[0]) + sum(ef[1])))
+        for e, f in pairs:
+            self.need(e, f, 0)
+        return es, fs
+
+    def flops(self):
+        """Floating-point operations per primitive quartet (FMA = 2):
+        A*x1 (1) + W*x2 (2) [+ c*(x3 - r*x4) (4)] [+ c5*x5 (2)] per node,
+        plus one add per accumulated target."""
+        fl = 0
+        for n in self.order:
+            d = n.deps
+            fl += 3
+            if "x3" in d:
+                fl += 4
+            if "x5" in d:
+                fl += 2
+        es, fs = self.targets()
+        return fl + len(es) * len(fs)
+
+
+def best_vrr(la, lb, lc, ld):
+    best = None
+    for lam in (0.0, 0.5, 1.0, 2.0, 4.0):
+        v = VRR(la, lb, lc, ld, lam)
+        v.build()
+        key = (v.flops(), len(v.order))
+        if best is None or key < best[0]:
+            best = (key, v)
+    return best[1]
+
+
+# --------------------------------------------------------------------------
+# HRR DAG (one side); each node is a vector over the other side's components
+# --------------------------------------------------------------------------
+
+class HRR:
+    """(a, b| from [e0| with |e| in [la, la+lb]: (a,b| = (a+1_i, b-1_i| + X_i (a, b-1_i|."""
+
+    def __init__(self, la, lb):
+        self.la, self.lb = la, lb
+        self.nodes = {}
+        self.order = []
+
+    def need(self, a, b):
+        key = (a, b)
+        if key in self.nodes:
+            return self.nodes[key]
+        if b == ZERO3:
+            self.nodes[key] = ("base", a)
+            return self.nodes[key]
+        best = None
+        for i in range(3):
+            if b[i] == 0:
+                continue
+            ch = [(add(a, i), sub(b, i)), (a, sub(b, i))]
+            r = sum(1 for c in ch if c in self.nodes)
+            cost = (2 - r, i)
+            if best is None or cost < best[0]:
+                best = (cost, i, ch)
+        _, i, ch = best
+        self.need(*ch[0])
+        self.need(*ch[1])
+        node = ("hrr", a, b, i, ch[0], ch[1], len(self.order))
+        self.nodes[key] = node
+        self.order.append(node)
+        return node
+
+    def build(self):
+        for a in cart(self.la):
+            for b in cart(self.lb):
+                self.need(a, b)
+        return self
+
+    def count(self):
+        return len(self.order)
+
+
+# --------------------------------------------------------------------------
+# Code emission
+# --------------------------------------------------------------------------
+
+def cls_name(la, lb, lc, ld):
+    s = "spdfgh"
+    return f"{s[la]}{s[lb]}{s[lc]}{s[ld]}"
+
+
+class ClassCode:
+    def __init__(self, la, lb, lc, ld):
+        self.la, self.lb, self.lc, self.ld = la, lb, lc, ld
+        self.name = cls_name(la, lb, lc, ld)
+        self.vrr = best_vrr(la, lb, lc, ld)
+        self.es, self.fs = self.vrr.build()
+        self.eidx = {e: k for k, e in enumerate(self.es)}
+        self.fidx = {f: k for k, f in enumerate(self.fs)}
+        self.nacc = len(self.es) * len(self.fs)
+        self.hb = HRR(la, lb).build()
+        self.hk = HRR(lc, ld).build()
+        nE, nF = len(self.es), len(self.fs)
+        nab, ncd = ncart(la) * ncart(lb), ncart(lc) * ncart(ld)
+        cost_bra_first = self.hb.count() * nF + nab * self.hk.count()
+        cost_ket_first = self.hk.count() * nE + ncd * self.hb.count()
+        self.bra_first = cost_bra_first <= cost_ket_first
+        self.hrr_flops = 2 * min(cost_bra_first, cost_ket_first)
+        self.nout = nab * ncd
+
+    # ---- VRR ----
+    def emit_vrr(self):
+        v = self.vrr
+        L = v.L
+        lines = []
+        lines.append("template <typename T>")
+        lines.append(f"__device__ __forceinline__ void vrr_{self.name}(const T* __restrict__ F, const VrrGeom<T>& g, "
+                     f"T* __restrict__ acc)")
+        lines.append("{")
+        lines.append(f"    // [e0|f0]^(0) for |e| in [{self.la},{self.la + self.lb}], |f| in [{self.lc},"
+                     f"{self.lc + self.ld}]; {len(v.order)} intermediates, m <= {L}")
+        need_oo2p = any(n.side == "b" and "x3" in n.deps for n in v.order)
+        need_oo2q = any(n.side == "k" and "x3" in n.deps for n in v.order)
+        need_oo2pq = any("x5" in n.deps for n in v.order)
+        targets = {}
+        for e in self.es:
+            for f in self.fs:
+                targets[(e, f, 0)] = self.eidx[e] * len(self.fs) + self.fidx[f]
+        consts = {}
+
+        def coef(kind, k):
+            key = (kind, k)
+            if key not in consts:
+                nm = f"c_{kind}{k}"
+                base = {"p": "g.oo2p", "q": "g.oo2q", "pq": "g.oo2pq"}[kind]
+                if k == 1:
+                    consts[key] = base
+                else:
+                    consts[key] = nm
+                    lines.append(f"    const T {nm} = T({k}) * {base};")
+            return consts[key]
+
+        del need_oo2p, need_oo2q, need_oo2pq
+        for n in v.order:
+            d = n.deps
+            i = n.axis
+            if n.side == "b":
+                A, W, rr, kind, cnt = f"g.PA[{i}]", f"g.WP[{i}]", "g.rho_p", "p", n.e[i] - 1
+                ocnt = n.f[i]
+            else:
+                A, W, rr, kind, cnt = f"g.QC[{i}]", f"g.WQ[{i}]", "g.rho_q", "q", n.f[i] - 1
+                ocnt = n.e[i]
+            expr = f"{A} * {d['x1'].name} + {W} * {d['x2'].name}"
+            if "x3" in d:
+                c = coef(kind, cnt)
+                expr += f" + {c} * ({d['x3'].name} - {rr} * {d['x4'].name})"
+            if "x5" in d:
+                c = coef("pq", ocnt)
+                expr += f" + {c} * {d['x5'].name}"
+            key = (n.e, n.f, n.m)
+            lines.append(f"    const T {n.name} = {expr};")
+            if key in targets:
+                lines.append(f"    acc[{targets[key]}] += {n.name};")
+        # targets that are base nodes ([00|00]^(0) for the (ss|ss) class)
+        for key, k in targets.items():
+            node = v.nodes[key]
+            if node.side == "":
+                lines.append(f"    acc[{k}] += {node.name};")
+        lines.append("}")
+        return "\n".join(lines)
+
+    # ---- HRR ----
+    def emit_hrr(self):
+        la, lb, lc, ld = self.la, self.lb, self.lc, self.ld
+        nb, nc, nd = ncart(lb), ncart(lc), ncart(ld)
+        nF = len(self.fs)
+        lines = []
+        lines.append("template <typename T>")
+        lines.append(f"__device__ __forceinline__ void hrr_{self.name}(const T* __restrict__ acc, const T AB[3], "
+                     f"const T CD[3], T* __restrict__ out)")
+        lines.append("{")
+        hb, hk = self.hb, self.hk
+
+        def bra_name(node_key, fk):
+            node = hb.nodes[node_key]
+            if node[0] == "base":
+                return f"acc[{self.eidx[node[1]] * nF + fk}]"
+            return f"hb{node[6]}_{fk}"
+
+        if self.bra_first:
+            # (ab|f] for every f, then the ket HRR for every (ab)
+            for fk in range(nF):
+                for node in hb.order:
+                    _, a, b, i, c0, c1, k = node
+                    lines.append(f"    const T hb{k}_{fk} = {bra_name(c0, fk)} + AB[{i}] * {bra_name(c1, fk)};")
+
+            def abf(a, b, f):
+                return bra_name((a, b), self.fidx[f])
+
+            for a in cart(la):
+                for b in cart(lb):
+                    ab = cidx(a) * nb + cidx(b)
+                    tag = f"{ab}"
+                    names = {}
+
+                    def kn(key):
+                        node = hk.nodes[key]
+                        if node[0] == "base":
+                            return abf(a, b, node[1])
+                        return names[key]
+
+                    for node in hk.order:
+                        _, c, d, i, c0, c1, k = node
+                        nm = f"hk{k}_{tag}"
+                        lines.append(f"    const T {nm} = {kn(c0)} + CD[{i}] * {kn(c1)};")
+                        names[(c, d)] = nm
+                    for c in cart(lc):
+                        for d in cart(ld):
+                            o = (ab * nc + cidx(c)) * nd + cidx(d)
+                            lines.append(f"    out[{o}] = {kn((c, d))};")
+        else:
+            nE = len(self.es)
+
+            def ket_name(node_key, ek):
+                node = hk.nodes[node_key]
+                if node[0] == "base":
+                    return f"acc[{ek * nF + self.fidx[node[1]]}]"
+                return f"hk{node[6]}_{ek}"
+
+            for ek in range(nE):
+                for node in hk.order:
+                    _, c, d, i, c0, c1, k = node
+                    lines.append(f"    const T hk{k}_{ek} = {ket_name(c0, ek)} + CD[{i}] * {ket_name(c1, ek)};")
+
+            def ecd(e, c, d):
+                return ket_name((c, d), self.eidx[e])
+
+            for c in cart(lc):
+                for d in cart(ld):
+                    cd = cidx(c) * nd + cidx(d)
+                    tag = f"{cd}"
+                    names = {}
+
+                    def bn(key):
+                        node = hb.nodes[key]
+                        if node[0] == "base":
+                            return ecd(node[1], c, d)
+                        return names[key]
+
+                    for node in hb.order:
+                        _, a, b, i, c0, c1, k = node
+                        nm = f"hb{k}_{tag}"
+                        lines.append(f"    const T {nm} = {bn(c0)} + AB[{i}] * {bn(c1)};")
+                        names[(a, b)] = nm
+                    for a in cart(la):
+                        for b in cart(lb):
+                            o = ((cidx(a) * nb + cidx(b)) * nc + cidx(c)) * nd + cidx(d)
+                            lines.append(f"    out[{o}] = {bn((a, b))};")
+        lines.append("}")
+        return "\n".join(lines)
+
+    def info(self):
+        return {
+            "class": self.name, "L": self.vrr.L, "nacc": self.nacc, "nout": self.nout,
+            "vrr_nodes": len(self.vrr.order), "vrr_flops": self.vrr.flops(), "vrr_lambda": self.vrr.lam,
+            "hrr_flops": self.hrr_flops, "hrr_bra_first": self.bra_first,
+        }
+
+
+def pair_classes(lmax):
+    return [(la, lb) for la in range(lmax + 1) for lb in range(la + 1)]
+
+
+def quartet_classes(lmax):
+    pcs = pair_classes(lmax)
+    out = []
+    for X in range(len(pcs)):
+        for Y in range(X + 1):
+            out.append(pcs[X] + pcs[Y])
+    return out
+
+
+HEADER = """// Generated by paper_2412_13203_amd/gen/eri_gen.py -- do not edit.
+// Obara-Saika vertical and Head-Gordon-Pople horizontal recurrences per
+// angular-momentum class; path chosen by the greedy search of Section 6.
+#pragma once
+"""
+
+
+def emit_trait(cc):
+    la, lb, lc, ld = cc.la, cc.lb, cc.lc, cc.ld
+    return "\n".join([
+        "template <>",
+        f"struct EriClass<{la}, {lb}, {lc}, {ld}> {{",
+        f"    static constexpr int NACC = {cc.nacc};",
+        f"    static constexpr int NOUT = {cc.nout};",
+        "    template <typename T>",
+        "    __device__ static __forceinline__ void vrr(const T *F, const VrrGeom<T> &g, T *acc)",
+        f"    {{ vrr_{cc.name}<T>(F, g, acc); }}",
+        "    template <typename T>",
+        "    __device__ static __forceinline__ void hrr(const T *acc, const T AB[3], const T CD[3], T *out)",
+        f"    {{ hrr_{cc.name}<T>(acc, AB, CD, out); }}",
+        "};",
+    ])
+
+
+def _write(path, text):
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        fh.write(text)
+    os.replace(tmp, path)
+
+
+def generate(outdir, lmax=2):
+    """Write eri_classes.inc, one translation unit per class, dispatch.inc."""
+    os.makedirs(outdir, exist_ok=True)
+    infos = []
+    body = [HEADER]
+    classes = quartet_classes(lmax)
+    ccs = []
+    for la, lb, lc, ld in classes:
+        cc = ClassCode(la, lb, lc, ld)
+        ccs.append(cc)
+        body.append(cc.emit_vrr())
+        body.append(cc.emit_hrr())
+        body.append(emit_trait(cc))
+        infos.append(cc.info())
+    _write(os.path.join(outdir, "eri_classes.inc"), "\n\n".join(body) + "\n")
+    tus = []
+    for cc in ccs:
+        lines = ["// Generated by paper_2412_13203_amd/gen/eri_gen.py -- do not edit.",
+                 '#include "../kernels.hpp"', "namespace mjk {",
+                 f"MJK_DEFINE_CLASS({cc.la}, {cc.lb}, {cc.lc}, {cc.ld}, {cc.name})"]
+        if (cc.la, cc.lb) == (cc.lc, cc.ld):
+            lines.append(f"MJK_DEFINE_SCHWARZ({cc.la}, {cc.lb}, {cc.name[:2]})")
+        lines.append("}  // namespace mjk")
+        path = os.path.join(outdir, f"tu_{cc.name}.hip")
+        _write(path, "\n".join(lines) + "\n")
+        tus.append(path)
+    # dispatch table, indexed by quartet class X(X+1)/2 + Y over pair classes
+    d = ["// Generated by paper_2412_13203_amd/gen/eri_gen.py -- do not edit.", "#pragma once",
+         '#include "../mjk_types.hpp"', "namespace mjk {"]
+    for cc in ccs:
+        d.append(f"int launch_jk_{cc.name}(const JKLaunch &, hipStream_t);")
+        d.append(f"int launch_eri_{cc.name}(const EriLaunch &, hipStream_t);")
+        if (cc.la, cc.lb) == (cc.lc, cc.ld):
+            d.append(f"int launch_schwarz_{cc.name[:2]}(const SchwarzLaunch &, hipStream_t);")
+    d.append(f"constexpr int kLmax = {lmax};")
+    d.append(f"constexpr int kNumPairClasses = {len(pair_classes(lmax))};")
+    d.append(f"constexpr int kNumQuartetClasses = {len(ccs)};")
+    d.append("static const ClassEntry kClassTable[kNumQuartetClasses] = {")
+    for cc in ccs:
+        sch = f"launch_schwarz_{cc.name[:2]}" if (cc.la, cc.lb) == (cc.lc, cc.ld) else "nullptr"
+        d.append(f"    {{{cc.la}, {cc.lb}, {cc.lc}, {cc.ld}, {cc.nacc}, {cc.nout}, {cc.vrr.flops()}, "
+                 f"{cc.hrr_flops}, launch_jk_{cc.name}, launch_eri_{cc.name}, {sch}}},")
+    d.append("};")
+    d.append("}  // namespace mjk")
+    _write(os.path.join(outdir, "dispatch.inc"), "\n".join(d) + "\n")
+    with open(os.path.join(outdir, "opcount.json"), "w") as fh:
+        json.dump(infos, fh, indent=1)
+    return infos, tus
+
+
+if __name__ == "__main__":
+    out = sys.argv[1] if len(sys.argv) > 1 else "gen_out"
+    lmax = int(sys.argv[2]) if len(sys.argv) > 2 else 2
+    infos, tus = generate(out, lmax)
+    for i in infos:
+        print(i)

@@ -1,0 +1,246 @@
+"""Thin Python binding of the C ABI in include/mjk.h (argument marshalling only).
+
+Every step of the ERI / J-K path runs in the HIP library
+paper_2412_13203_amd/_lib/libmjk.so; torch provides device memory and the
+stream.  There is no fallback: if the library or a gfx950 device is missing,
+calls raise.
+
+    plan = Plan(basis, tau=1e-10)          # mjk_plan_create + mjk_plan_bind
+    J, K = plan.build_jk(D)                # mjk_build_jk
+    blocks = plan.eri_class(quartets)      # mjk_eri_class
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libmjk.so")
+
+MJK_OK = 0
+ERRORS = {-1: "MJK_ERR_INVALID_ARG", -2: "MJK_ERR_UNSUPPORTED", -3: "MJK_ERR_NO_DEVICE", -4: "MJK_ERR_WORKSPACE",
+          -5: "MJK_ERR_HIP", -6: "MJK_ERR_STATE"}
+FLAG_CHECK = 0x1
+
+
+class MjkError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Basis(ctypes.Structure):
+    _fields_ = [
+        ("natom", ctypes.c_int32),
+        ("xyz", ctypes.POINTER(ctypes.c_double)),
+        ("nshell", ctypes.c_int32),
+        ("shell_atom", ctypes.POINTER(ctypes.c_int32)),
+        ("shell_l", ctypes.POINTER(ctypes.c_int32)),
+        ("shell_nprim", ctypes.POINTER(ctypes.c_int32)),
+        ("shell_prim_off", ctypes.POINTER(ctypes.c_int32)),
+        ("nprim", ctypes.c_int64),
+        ("exps", ctypes.POINTER(ctypes.c_double)),
+        ("coefs", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class JKOpts(ctypes.Structure):
+    _fields_ = [("schwarz_tau", ctypes.c_double), ("fp32_tau", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [
+        ("nbf", ctypes.c_int64), ("nshell", ctypes.c_int64), ("npair", ctypes.c_int64),
+        ("nprim_pair", ctypes.c_int64), ("nquartet_total", ctypes.c_int64), ("nquartet_kept", ctypes.c_int64),
+        ("nprim_quartet_kept", ctypes.c_int64), ("ncart_eri_kept", ctypes.c_int64), ("nlaunch", ctypes.c_int64),
+        ("vrr_flops_kept", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ClassTiming(ctypes.Structure):
+    _fields_ = [("la", ctypes.c_int32), ("lb", ctypes.c_int32), ("lc", ctypes.c_int32), ("ld", ctypes.c_int32),
+                ("nlaunch", ctypes.c_int32), ("ms", ctypes.c_double), ("nquartet", ctypes.c_int64),
+                ("nprim_quartet", ctypes.c_int64), ("flops", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["cls"] = "".join("spdf"[d[k]] for k in ("la", "lb", "lc", "ld"))
+        return d
+
+
+_lib = None
+
+# exported names of include/mjk.h
+EXPORTS = ["mjk_lmax", "mjk_last_error", "mjk_ctx_create", "mjk_ctx_destroy", "mjk_nbf", "mjk_plan_create",
+           "mjk_plan_bind", "mjk_build_jk", "mjk_eri_class", "mjk_schwarz", "mjk_plan_stats_get",
+           "mjk_plan_set_timing", "mjk_plan_timings", "mjk_plan_destroy"]
+
+
+def lib():
+    """Load libmjk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MjkError(-3, f"{LIB_PATH} is missing: run `python -m paper_2412_13203_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.mjk_lmax.restype = ctypes.c_int
+        L.mjk_last_error.restype = ctypes.c_char_p
+        L.mjk_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+        L.mjk_ctx_destroy.argtypes = [vp]
+        L.mjk_ctx_destroy.restype = None
+        L.mjk_nbf.argtypes = [ctypes.POINTER(Basis), ctypes.POINTER(i64)]
+        L.mjk_plan_create.argtypes = [vp, ctypes.POINTER(Basis), ctypes.POINTER(JKOpts), ctypes.POINTER(vp),
+                                      ctypes.POINTER(sz)]
+        L.mjk_plan_bind.argtypes = [vp, vp, sz, vp]
+        L.mjk_build_jk.argtypes = [vp, vp, vp, vp, vp]
+        L.mjk_eri_class.argtypes = [vp, ctypes.POINTER(i32), i64, vp, i64, vp]
+        L.mjk_schwarz.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.mjk_plan_stats_get.argtypes = [vp, ctypes.POINTER(PlanStats)]
+        L.mjk_plan_set_timing.argtypes = [vp, ctypes.c_int]
+        L.mjk_plan_timings.argtypes = [vp, ctypes.POINTER(ClassTiming), i32, ctypes.POINTER(i32)]
+        L.mjk_plan_destroy.argtypes = [vp]
+        L.mjk_plan_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != MJK_OK:
+        raise MjkError(rc, lib().mjk_last_error().decode())
+
+
+class _HostBasis:
+    """Contiguous host arrays + the mjk_basis struct that points at them."""
+
+    def __init__(self, basis: dict):
+        self.xyz = np.ascontiguousarray(basis["xyz"], dtype=np.float64)
+        self.atom = np.ascontiguousarray(basis["shell_atom"], dtype=np.int32)
+        self.l = np.ascontiguousarray(basis["shell_l"], dtype=np.int32)
+        self.nprim = np.ascontiguousarray(basis["shell_nprim"], dtype=np.int32)
+        self.off = np.ascontiguousarray(basis["shell_prim_off"], dtype=np.int32)
+        self.exps = np.ascontiguousarray(basis["exps"], dtype=np.float64)
+        self.coefs = np.ascontiguousarray(basis["coefs"], dtype=np.float64)
+        d = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # noqa: E731
+        i = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
+        self.s = Basis(self.xyz.shape[0], d(self.xyz), len(self.l), i(self.atom), i(self.l), i(self.nprim),
+                       i(self.off), len(self.exps), d(self.exps), d(self.coefs))
+        self.ncart = (self.l + 1) * (self.l + 2) // 2
+
+
+def nbf(basis: dict) -> int:
+    h = _HostBasis(basis)
+    n = ctypes.c_int64(0)
+    _check(lib().mjk_nbf(ctypes.byref(h.s), ctypes.byref(n)))
+    return int(n.value)
+
+
+_ctx = {}
+
+
+def context(device: int = 0):
+    if device not in _ctx:
+        c = ctypes.c_void_p()
+        _check(lib().mjk_ctx_create(device, ctypes.byref(c)))
+        _ctx[device] = c
+    return _ctx[device]
+
+
+def _stream(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """A bound plan: tables for one basis/geometry in a torch-owned workspace."""
+
+    def __init__(self, basis: dict, tau: float = 0.0, flags: int = 0, device: int = 0):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.basis = basis
+        self._hb = _HostBasis(basis)
+        ctx = context(device)
+        opts = JKOpts(float(tau), 0.0, int(flags))
+        p = ctypes.c_void_p()
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().mjk_plan_create(ctx, ctypes.byref(self._hb.s), ctypes.byref(opts), ctypes.byref(p),
+                                     ctypes.byref(nbytes)))
+        self._p = p
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=f"cuda:{device}")
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        _check(lib().mjk_plan_bind(p, ctypes.c_void_p(aligned), ctypes.c_size_t(int(nbytes.value)),
+                                   _stream(torch, device)))
+        st = PlanStats()
+        _check(lib().mjk_plan_stats_get(p, ctypes.byref(st)))
+        self.stats = st.as_dict()
+        self.nbf = int(st.nbf)
+
+    def __del__(self):
+        p = getattr(self, "_p", None)
+        if p is not None and p.value and _lib is not None:
+            _lib.mjk_plan_destroy(p)
+            self._p = None
+
+    def build_jk(self, D, J=None, K=None):
+        """J, K (torch float64 on the plan's device) for symmetric density D."""
+        torch = self.torch
+        D = torch.as_tensor(D, dtype=torch.float64, device=f"cuda:{self.device}").contiguous()
+        n = self.nbf
+        if D.shape != (n, n):
+            raise MjkError(-1, f"D has shape {tuple(D.shape)}, expected ({n}, {n})")
+        if J is None:
+            J = torch.empty((n, n), dtype=torch.float64, device=D.device)
+        if K is None:
+            K = torch.empty((n, n), dtype=torch.float64, device=D.device)
+        _check(lib().mjk_build_jk(self._p, ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(J.data_ptr()),
+                                  ctypes.c_void_p(K.data_ptr()), _stream(torch, self.device)))
+        return J, K
+
+    def eri_class(self, quartets):
+        """Contracted ERI blocks for shell quartets (nq x 4), as a list of (na,nb,nc,nd) tensors."""
+        torch = self.torch
+        q = np.ascontiguousarray(np.asarray(quartets, dtype=np.int32).reshape(-1, 4))
+        nc = self._hb.ncart
+        sizes = [int(nc[a] * nc[b] * nc[c] * nc[d]) for a, b, c, d in q] if len(q) else []
+        total = int(sum(sizes))
+        out = torch.empty(max(total, 1), dtype=torch.float64, device=f"cuda:{self.device}")
+        _check(lib().mjk_eri_class(self._p, q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(q),
+                                   ctypes.c_void_p(out.data_ptr()), total, _stream(torch, self.device)))
+        res, o = [], 0
+        for (a, b, c, d), s in zip(q, sizes):
+            res.append(out[o:o + s].view(int(nc[a]), int(nc[b]), int(nc[c]), int(nc[d])))
+            o += s
+        return res
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().mjk_plan_set_timing(self._p, int(bool(enable))))
+
+    def timings(self):
+        """Per-class kernel times of the last build_jk (call after the stream completed)."""
+        cap = 256
+        arr = (ClassTiming * cap)()
+        n = ctypes.c_int32(0)
+        _check(lib().mjk_plan_timings(self._p, arr, cap, ctypes.byref(n)))
+        return [arr[i].as_dict() for i in range(min(n.value, cap))]
+
+    def schwarz(self):
+        ns = len(self._hb.l)
+        Q = np.zeros((ns, ns))
+        _check(lib().mjk_schwarz(self._p, Q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return Q
+
+
+def build_jk(basis: dict, D, tau: float = 0.0, device: int = 0):
+    """One-shot J, K for `basis` and density `D` (plans and binds each call)."""
+    plan = Plan(basis, tau=tau, device=device)
+    return plan.build_jk(D)
+
+
+def eri_class(basis: dict, quartets, device: int = 0):
+    return Plan(basis, device=device).eri_class(quartets)

@@ -1,0 +1,207 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bar (FP64): 1e-10 absolute per ERI and per J/K element.  Atomic accumulation
+order varies from run to run, so J/K are compared to that bar, not bitwise.
+Quartet counts (integer work) must match the oracle exactly.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_13203_amd import inputs, mjk
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    mjk.context(0)
+    return torch
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _close(a, b, tol=TOL, what=""):
+    d = float(np.max(np.abs(np.asarray(a) - np.asarray(b))))
+    assert d <= tol, f"{what} max abs diff {d:.3e} > {tol:.1e}"
+    return d
+
+
+def _ls_basis(seed):
+    """Three atoms with s, p, d shells (1-3 primitives): every l combination."""
+    rng = np.random.default_rng(seed)
+    return inputs.random_shells(rng, 3, [0, 1, 2, 1, 0], box=2.5, nprim_range=(1, 3), exp_range=(0.15, 8.0))
+
+
+def test_eri_class_every_ordered_class():
+    b = _ls_basis(101)
+    ls = b["shell_l"]
+    by_l = {l: [s for s in range(len(ls)) if ls[s] == l] for l in range(3)}
+    rng = np.random.default_rng(5)
+    quartets = []
+    for combo in itertools.product(range(3), repeat=4):
+        for _ in range(2):
+            quartets.append([int(rng.choice(by_l[l])) for l in combo])
+    plan = mjk.Plan(b)
+    blocks = plan.eri_class(quartets)
+    worst = 0.0
+    for q, g in zip(quartets, blocks):
+        ref = oracle.eri_block(b, *q)
+        d = np.max(np.abs(_np(g) - ref))
+        worst = max(worst, d)
+        assert d <= TOL, (q, d)
+    print("eri_class worst abs diff", worst)
+
+
+def test_config1_full_tensor_and_jk(gpu):
+    cfg = inputs.make_config(1)
+    b, D = cfg["basis"], cfg["D"]
+    ns = len(b["shell_l"])
+    off = inputs.ao_offsets(b)
+    T = oracle.eri_tensor(b)
+    plan = mjk.Plan(b, tau=0.0)
+    quartets = list(itertools.product(range(ns), repeat=4))
+    blocks = plan.eri_class(quartets)
+    G = np.zeros_like(T)
+    for (A, B, C, Dd), blk in zip(quartets, blocks):
+        G[off[A]:off[A + 1], off[B]:off[B + 1], off[C]:off[C + 1], off[Dd]:off[Dd + 1]] = _np(blk)
+    _close(G, T)
+    J, K = plan.build_jk(D)
+    Jref = np.einsum("mnls,ls->mn", T, D)
+    Kref = np.einsum("mlns,ls->mn", T, D)
+    _close(_np(J), Jref)
+    _close(_np(K), Kref)
+    npair = ns * (ns + 1) // 2
+    assert plan.stats["nquartet_kept"] == npair * (npair + 1) // 2
+
+
+def test_schwarz_matches_oracle():
+    cfg = inputs.make_config(2, natom=6)
+    b = cfg["basis"]
+    plan = mjk.Plan(b, tau=1e-10)
+    Qg = plan.schwarz()
+    Qo = oracle.schwarz(b)
+    # Q^2 is an integral (ab|ab): the FP64 bar of 1e-10 absolute per ERI
+    d2 = float(np.max(np.abs(Qg ** 2 - Qo ** 2)))
+    assert d2 <= TOL, d2
+    big = Qo > 1e-6
+    rel = float(np.max(np.abs(Qg - Qo)[big] / Qo[big]))
+    assert rel < 1e-11, rel
+
+
+def test_config2_recipe_small_full_oracle():
+    """8 atoms of the s,s,p,d lattice recipe with tau = 1e-10: full J, K."""
+    cfg = inputs.make_config(2, natom=8)
+    b, D, tau = cfg["basis"], cfg["D"], cfg["tau"]
+    plan = mjk.Plan(b, tau=tau)
+    J, K = plan.build_jk(D)
+    Jo, Ko, nq = oracle.build_jk(b, D, tau)
+    _close(_np(J), Jo)
+    _close(_np(K), Ko)
+    assert plan.stats["nquartet_kept"] == nq
+
+
+def test_config2_full_size_sampled_blocks():
+    """The 40-atom workload at its full size and screening, in the launch
+    configuration the benchmark times; sampled shell blocks against stored
+    oracle block sums, plus properties that hold at any size."""
+    cfg = inputs.make_config(2)
+    b, D = cfg["basis"], cfg["D"]
+    gold = json.load(open(os.path.join(HERE, "golden", "config2_jk_blocks.json")))
+    plan = mjk.Plan(b, tau=gold["tau"])
+    J, K = plan.build_jk(D)
+    J, K = _np(J), _np(K)
+    off = inputs.ao_offsets(b)
+    for (A, B), jv, kv in zip(gold["blocks"], gold["J"], gold["K"]):
+        sa, sb = slice(off[A], off[A + 1]), slice(off[B], off[B + 1])
+        _close(J[sa, sb].ravel(), np.array(jv), what=str((A, B)))
+        _close(K[sa, sb].ravel(), np.array(kv), what=str((A, B)))
+    assert np.array_equal(J, J.T) and np.array_equal(K, K.T)
+    tj, tk = np.sum(D * J), np.sum(D * K)
+    assert 0 < tk <= tj * (1 + 1e-12)
+
+
+def test_probe_density_ties_jk_to_eri_class():
+    cfg = inputs.make_config(2, natom=3)
+    b = cfg["basis"]
+    N = b["nbf"]
+    off = inputs.ao_offsets(b)
+    plan = mjk.Plan(b)
+    # i in shell 3 (d), j in shell 6 (p)
+    i, j = off[3] + 1, off[6] + 2
+    Dp = np.zeros((N, N))
+    Dp[i, j] = Dp[j, i] = 1.0
+    J, _ = plan.build_jk(Dp)
+    ns = len(b["shell_l"])
+    quartets = [(A, B, 3, 6) for A in range(ns) for B in range(ns)]
+    blocks = plan.eri_class(quartets)
+    ref = np.zeros((N, N))
+    for (A, B, _, _), blk in zip(quartets, blocks):
+        ref[off[A]:off[A + 1], off[B]:off[B + 1]] = 2 * _np(blk)[:, :, 1, 2]
+    _close(_np(J), ref)
+
+
+def test_edge_single_s_shell():
+    b = {"xyz": np.zeros((1, 3)), "shell_atom": np.array([0], np.int32), "shell_l": np.array([0], np.int32),
+         "shell_nprim": np.array([2], np.int32), "shell_prim_off": np.array([0], np.int32),
+         "exps": np.array([0.5, 2.0]), "coefs": np.array([0.4, 0.7]), "nbf": 1}
+    plan = mjk.Plan(b)
+    D = np.array([[0.8]])
+    J, K = plan.build_jk(D)
+    v = oracle.eri_block(b, 0, 0, 0, 0)[0, 0, 0, 0]
+    assert abs(_np(J)[0, 0] - v * 0.8) <= TOL
+    assert abs(_np(K)[0, 0] - v * 0.8) <= TOL
+
+
+def test_edge_mixed_primitive_counts_and_coincident_centres():
+    rng = np.random.default_rng(77)
+    b = inputs.random_shells(rng, 4, [0, 1, 2, 0], box=2.0, nprim_range=(1, 6), exp_range=(0.1, 20.0))
+    b["xyz"][3] = b["xyz"][2]  # two atoms on one site
+    C = rng.standard_normal((b["nbf"], 5)) * 0.3
+    D = C @ C.T
+    D = 0.5 * (D + D.T)
+    plan = mjk.Plan(b, tau=0.0)
+    J, K = plan.build_jk(D)
+    Jo, Ko, nq = oracle.build_jk(b, D, 0.0)
+    _close(_np(J), Jo)
+    _close(_np(K), Ko)
+    assert plan.stats["nquartet_kept"] == nq
+
+
+def test_repeat_run_spread():
+    cfg = inputs.make_config(2, natom=5)
+    plan = mjk.Plan(cfg["basis"], tau=1e-10)
+    J1, K1 = plan.build_jk(cfg["D"])
+    J1, K1 = _np(J1), _np(K1)
+    J2, K2 = plan.build_jk(cfg["D"])
+    _close(_np(J2), J1, 1e-13 * float(np.max(np.abs(J1))))
+    _close(_np(K2), K1, 1e-13 * float(np.max(np.abs(K1))))
+
+
+def test_screening_changes_counts_consistently():
+    cfg = inputs.make_config(2, natom=8)
+    b, D = cfg["basis"], cfg["D"]
+    Q = oracle.schwarz(b)
+    ns = len(b["shell_l"])
+    qp = np.array([Q[A, B] for A in range(ns) for B in range(A + 1)])
+    prod = np.outer(qp, qp)
+    for tau in (1e-6, 1e-3):
+        # no quartet may sit within 1e-9 (relative) of the threshold, where
+        # rounding of Q could decide it differently on the two sides
+        assert not np.any(np.abs(prod / tau - 1.0) < 1e-9)
+        plan = mjk.Plan(b, tau=tau)
+        J, K = plan.build_jk(D)
+        Jo, Ko, nq = oracle.build_jk(b, D, tau, Q)
+        assert plan.stats["nquartet_kept"] == nq
+        _close(_np(J), Jo)
+        _close(_np(K), Ko)

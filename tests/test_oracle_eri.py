@@ -24,7 +24,6 @@ from scipy.special import erf
 import oracle
 from paper_2412_13203_amd import inputs
 
-mpmath.mp.dps = 30
 
 
 def prim_basis(centres, exps, ls):
@@ -84,6 +83,11 @@ def _op_poly(n, alpha):
 
 def prim_eri_by_derivatives(centres, exps, cart):
     """[ab|cd] for Cartesian exponent triples cart[k] = (i, j, k) on centre k."""
+    with mpmath.workdps(30):
+        return _prim_eri_by_derivatives(centres, exps, cart)
+
+
+def _prim_eri_by_derivatives(centres, exps, cart):
     x0 = [mpmath.mpf(v) for c in centres for v in c]
     ex = [mpmath.mpf(v) for v in exps]
     polys = []
