@@ -44,9 +44,8 @@ def cpu_baseline(cfg, target_s=15.0):
     t0 = time.time()
     _, _, nq = oracle.jk_rows(b, D, tau, rows, Q)
     dt = time.time() - t0
-    if dt < target_s / 4:
-        scale = max(1, int(target_s / max(dt, 1e-3)))
-        stride = max(8, stride // scale)
+    if dt < target_s / 2:
+        stride = max(8, int(stride * max(dt, 1e-3) / target_s))
         rows = np.arange(stride // 2, npair, stride, dtype=np.int32)
         t0 = time.time()
         _, _, nq = oracle.jk_rows(b, D, tau, rows, Q)
