@@ -60,7 +60,7 @@ def _compile(src, verbose):
     return obj
 
 
-def build(verbose: bool = True, jobs: int | None = None, lmax: int = 2) -> str:
+def build(verbose: bool = True, jobs: int | None = None, lmax: int = 2, out: str | None = None) -> str:
     t0 = time.time()
     tus = generate(lmax)
     if os.path.isdir(OBJDIR):
@@ -72,15 +72,17 @@ def build(verbose: bool = True, jobs: int | None = None, lmax: int = 2) -> str:
     jobs = jobs or min(16, os.cpu_count() or 4)
     with ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
-    tmp = LIB + ".tmp"
+    lib = out or LIB
+    os.makedirs(os.path.dirname(lib), exist_ok=True)
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB} in {time.time() - t0:.1f}s", flush=True)
-    return LIB
+        print(f"built {lib} in {time.time() - t0:.1f}s", flush=True)
+    return lib
 
 
 def _weight(tu):
@@ -92,5 +94,6 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--lmax", type=int, default=2)
+    ap.add_argument("--out", default=None, help="library path (default: _lib/libmjk.so)")
     args = ap.parse_args()
-    build(jobs=args.jobs, lmax=args.lmax)
+    build(jobs=args.jobs, lmax=args.lmax, out=args.out)

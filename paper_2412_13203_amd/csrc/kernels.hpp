@@ -24,6 +24,9 @@ struct VrrGeom {
 template <int LA, int LB, int LC, int LD>
 struct EriClass;
 
+template <int LA, int LB, int LC, int LD>
+struct EriSplit;
+
 }  // namespace mjk
 
 #include "gen/boys_table.inc"
@@ -120,11 +123,13 @@ __device__ __forceinline__ void contract_quartet(const ShellPairD &bra, const Sh
     constexpr int L = LA + LB + LC + LD;
 #pragma unroll
     for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
+    // ket primitives outer: each lane loads its own ket record once; the bra
+    // records are wave-uniform (scalar loads) in the inner loop
     const int nk = active ? ket.nprim : 0;
-    for (int ib = 0; ib < bra.nprim; ++ib) {
-        const PrimPairD bp = load_prim(prims + bra.prim_off + ib);
-        for (int ik = 0; ik < nk; ++ik) {
-            const PrimPairD kp = load_prim(prims + ket.prim_off + ik);
+    for (int ik = 0; ik < nk; ++ik) {
+        const PrimPairD kp = load_prim(prims + ket.prim_off + ik);
+        for (int ib = 0; ib < bra.nprim; ++ib) {
+            const PrimPairD bp = load_prim(prims + bra.prim_off + ib);
             VrrGeom<double> g;
             double T;
             const double pref = prim_geom(bp, kp, g, T);
@@ -347,6 +352,230 @@ __global__ __launch_bounds__(64) void k_schwarz(SchwarzLaunch a)
     for (int i = 0; i < NA * NB; ++i) mx = fmax(mx, eri[i * NA * NB + i]);
     a.Q[pi] = sqrt(mx);
 }
+
+// ---------------------------------------------------------------------------
+// Fused J/K for classes whose [e0|f0] accumulators do not fit one lane's
+// registers.  Same work items as k_jk (one bra pair x up to 64 kets), but
+//   phase 1: each lane runs the vertical recurrence in NPASS passes over its
+//            quartet's primitive quartets; a pass keeps only its subset of
+//            accumulators in registers and writes them to a per-slot staging
+//            buffer in global memory ([target][lane], coalesced);
+//   phase 2: the wave takes the item's quartets one at a time: [e0|f0] into
+//            LDS, bra HRR one ket column per lane, ket HRR one (ab) row per
+//            lane, then the six digestion contractions one output element per
+//            lane, with the bra-uniform Jt_ab kept per lane across the item.
+// Blocks are persistent (grid = staging slots) and stride over the items.
+// ---------------------------------------------------------------------------
+template <int LA, int LB, int LC, int LD, int P>
+__device__ __forceinline__ void split_pass(const ShellPairD &bra, const ShellPairD &ket,
+                                           const PrimPairD *__restrict__ prims, bool active,
+                                           double *__restrict__ stage, int lane)
+{
+    using S = EriSplit<LA, LB, LC, LD>;
+    constexpr int L = LA + LB + LC + LD;
+    constexpr int NP = S::template npass_acc<P>();
+    double acc[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) acc[i] = 0.0;
+    const int nk = active ? ket.nprim : 0;
+    for (int ik = 0; ik < nk; ++ik) {
+        const PrimPairD kp = load_prim(prims + ket.prim_off + ik);
+        for (int ib = 0; ib < bra.nprim; ++ib) {
+            const PrimPairD bp = load_prim(prims + bra.prim_off + ib);
+            VrrGeom<double> g;
+            double T;
+            const double pref = prim_geom(bp, kp, g, T);
+            double F[L + 1];
+            boys_fm<L>(T, F);
+#pragma unroll
+            for (int m = 0; m <= L; ++m) F[m] *= pref;
+            S::template vrr<P, double>(F, g, acc);
+        }
+    }
+    // The lane offset is made opaque here so that the compiler cannot hoist
+    // one 64-bit store address per target out of the item loop (that many
+    // live addresses would be spilled to scratch).
+    int off = lane;
+    __asm__ volatile("" : "+v"(off));
+    double *sl = stage + off;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) sl[S::template gmap<P>(j) * 64] = acc[j];
+}
+
+template <int LA, int LB, int LC, int LD, int P>
+__device__ __forceinline__ void split_passes(const ShellPairD &bra, const ShellPairD &ket,
+                                             const PrimPairD *__restrict__ prims, bool active,
+                                             double *__restrict__ stage, int lane)
+{
+    if constexpr (P < EriSplit<LA, LB, LC, LD>::NPASS) {
+        split_pass<LA, LB, LC, LD, P>(bra, ket, prims, active, stage, lane);
+        split_passes<LA, LB, LC, LD, P + 1>(bra, ket, prims, active, stage, lane);
+    }
+}
+
+template <int LA, int LB, int LC, int LD>
+__global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
+{
+    using S = EriSplit<LA, LB, LC, LD>;
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    constexpr int NAB = NA * NB, NCD = NC * ND, NF = S::NF, NACC = S::NACC;
+    constexpr int NBUF = NACC > NAB * NCD ? NACC : NAB * NCD;
+    __shared__ double s_buf[NBUF];     // [e][f], then (ab|cd) as [ab][cd]
+    __shared__ double s_abf[NAB * NF]; // (ab|f] as [ab][f]
+    __shared__ double s_Dab[NAB], s_Dcd[NCD], s_Dac[NA * NC], s_Dad[NA * ND], s_Dbc[NB * NC], s_Dbd[NB * ND];
+    __shared__ double s_CD[64][3];
+    __shared__ double s_w[64];
+    __shared__ int s_ao[64][2];
+    const int lane = threadIdx.x;
+    const int N = a.nbf;
+    const double *__restrict__ D = a.D;
+    double *stage = a.stage + (size_t)blockIdx.x * NACC * 64;
+
+    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+        int lo = 0, hi = a.nbra;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.chunk_prefix[mid] <= item)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int b = lo;
+        const int kbeg = (item - a.chunk_prefix[b]) * a.chunk;
+        const int kend = min(kbeg + a.chunk, a.ket_count[b]);
+        const int nact = min(kend - kbeg, 64);
+        const int bra_pos = a.bra_begin + b;
+        const ShellPairD bra = a.pairs[bra_pos];
+
+        // phase 1: one quartet per lane, passes into the staging slot
+        const int k = kbeg + lane;
+        const bool active = lane < nact;
+        const int ket_pos = a.ket_begin + (active ? k : kbeg);
+        const ShellPairD ket = a.pairs[ket_pos];
+        split_passes<LA, LB, LC, LD, 0>(bra, ket, a.prims, active, stage, lane);
+        {
+            double s = 1.0;
+            if (bra.same) s *= 2.0;
+            if (ket.same) s *= 2.0;
+            if (a.same_bin && ket_pos == bra_pos) s *= 2.0;
+            s_w[lane] = active ? 1.0 / s : 0.0;
+            s_CD[lane][0] = ket.AB[0];
+            s_CD[lane][1] = ket.AB[1];
+            s_CD[lane][2] = ket.AB[2];
+            s_ao[lane][0] = ket.ao_a;
+            s_ao[lane][1] = ket.ao_b;
+        }
+        for (int t = lane; t < NAB; t += 64) s_Dab[t] = D[(size_t)(bra.ao_a + t / NB) * N + bra.ao_b + t % NB];
+        __syncthreads();
+
+        // phase 2: the wave works through the item's quartets
+        double jab = 0.0;  // Jt_ab for ab = lane (lane < NAB), summed over the item
+        for (int q = 0; q < nact; ++q) {
+            for (int t = lane; t < NACC; t += 64) s_buf[t] = stage[(size_t)t * 64 + q];
+            const int ao_c = s_ao[q][0], ao_d = s_ao[q][1];
+            for (int t = lane; t < NCD; t += 64) s_Dcd[t] = D[(size_t)(ao_c + t / ND) * N + ao_d + t % ND];
+            for (int t = lane; t < NA * NC; t += 64) s_Dac[t] = D[(size_t)(bra.ao_a + t / NC) * N + ao_c + t % NC];
+            for (int t = lane; t < NA * ND; t += 64) s_Dad[t] = D[(size_t)(bra.ao_a + t / ND) * N + ao_d + t % ND];
+            for (int t = lane; t < NB * NC; t += 64) s_Dbc[t] = D[(size_t)(bra.ao_b + t / NC) * N + ao_c + t % NC];
+            for (int t = lane; t < NB * ND; t += 64) s_Dbd[t] = D[(size_t)(bra.ao_b + t / ND) * N + ao_d + t % ND];
+            __syncthreads();
+            for (int f = lane; f < NF; f += 64) S::template hrr_bra_col<double>(s_buf, f, bra.AB, s_abf);
+            __syncthreads();
+            const double CD[3] = {s_CD[q][0], s_CD[q][1], s_CD[q][2]};
+            const double w = s_w[q];
+            for (int r = lane; r < NAB; r += 64) {
+                double row[NCD];
+                S::template hrr_ket_row<double>(s_abf + r * NF, CD, row);
+                double t = 0.0;
+#pragma unroll
+                for (int cd = 0; cd < NCD; ++cd) {
+                    s_buf[r * NCD + cd] = row[cd];
+                    t += row[cd] * s_Dcd[cd];
+                }
+                jab += 2.0 * w * t;
+            }
+            __syncthreads();
+            // Jt_cd += 2w sum_ab (ab|cd) D_ab
+            for (int t = lane; t < NCD; t += 64) {
+                double v = 0.0;
+#pragma unroll
+                for (int ab = 0; ab < NAB; ++ab) v += s_buf[ab * NCD + t] * s_Dab[ab];
+                atomicAdd(a.J + (size_t)(ao_c + t / ND) * N + ao_d + t % ND, 2.0 * w * v);
+            }
+            // Kt_ac += w sum_{b,d} (ab|cd) D_bd
+            for (int t = lane; t < NA * NC; t += 64) {
+                const int ia = t / NC, c = t % NC;
+                double v = 0.0;
+#pragma unroll
+                for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dbd[jb * ND + d];
+                atomicAdd(a.K + (size_t)(bra.ao_a + ia) * N + ao_c + c, w * v);
+            }
+            // Kt_ad += w sum_{b,c} (ab|cd) D_bc
+            for (int t = lane; t < NA * ND; t += 64) {
+                const int ia = t / ND, d = t % ND;
+                double v = 0.0;
+#pragma unroll
+                for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dbc[jb * NC + c];
+                atomicAdd(a.K + (size_t)(bra.ao_a + ia) * N + ao_d + d, w * v);
+            }
+            // Kt_bc += w sum_{a,d} (ab|cd) D_ad
+            for (int t = lane; t < NB * NC; t += 64) {
+                const int jb = t / NC, c = t % NC;
+                double v = 0.0;
+#pragma unroll
+                for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dad[ia * ND + d];
+                atomicAdd(a.K + (size_t)(bra.ao_b + jb) * N + ao_c + c, w * v);
+            }
+            // Kt_bd += w sum_{a,c} (ab|cd) D_ac
+            for (int t = lane; t < NB * ND; t += 64) {
+                const int jb = t / ND, d = t % ND;
+                double v = 0.0;
+#pragma unroll
+                for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dac[ia * NC + c];
+                atomicAdd(a.K + (size_t)(bra.ao_b + jb) * N + ao_d + d, w * v);
+            }
+            __syncthreads();
+        }
+        if (lane < NAB) atomicAdd(a.J + (size_t)(bra.ao_a + lane / NB) * N + bra.ao_b + lane % NB, jab);
+        __syncthreads();
+    }
+}
+
+#define MJK_DEFINE_CLASS_SPLIT(LA, LB, LC, LD, NAME)                                                \
+    int launch_jk_##NAME(const JKLaunch &a, hipStream_t s)                                         \
+    {                                                                                               \
+        if (a.nitems <= 0) return 0;                                                                \
+        static int per_cu = -1;                                                                     \
+        static int ncu = 0;                                                                         \
+        if (per_cu < 0) {                                                                           \
+            int dev = 0;                                                                            \
+            hipGetDevice(&dev);                                                                     \
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);                \
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_jk_split<LA, LB, LC, LD>, 64, \
+                                                             0) != hipSuccess || per_cu < 1)        \
+                per_cu = 1;                                                                         \
+        }                                                                                           \
+        int grid = per_cu * ncu;                                                                    \
+        if (grid > a.nslot) grid = a.nslot;                                                         \
+        if (grid > a.nitems) grid = a.nitems;                                                       \
+        if (grid < 1) return -1;                                                                    \
+        hipLaunchKernelGGL((k_jk_split<LA, LB, LC, LD>), dim3(grid), dim3(64), 0, s, a);            \
+        return hipGetLastError() == hipSuccess ? 0 : -1;                                            \
+    }                                                                                               \
+    int launch_eri_##NAME(const EriLaunch &a, hipStream_t s)                                       \
+    {                                                                                               \
+        if (a.n <= 0) return 0;                                                                     \
+        hipLaunchKernelGGL((k_eri<LA, LB, LC, LD>), dim3((a.n + 63) / 64), dim3(64), 0, s, a);      \
+        return hipGetLastError() == hipSuccess ? 0 : -1;                                            \
+    }
 
 #define MJK_DEFINE_CLASS(LA, LB, LC, LD, NAME)                                                      \
     int launch_jk_##NAME(const JKLaunch &a, hipStream_t s)                                         \

@@ -73,6 +73,7 @@ inline int kbucket(int np)
 constexpr int kNumKBuckets = 6;
 constexpr int kChunk = 64;          // kets per work item (one per lane)
 constexpr int kEriStage = 65536;    // eri_class items per upload
+constexpr int kSlotsPerCU = 8;      // resident waves per CU the staging is sized for
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -122,7 +123,9 @@ struct mjk_plan {
     std::vector<std::vector<int32_t>> class_pairs;  // natural indices per pair class
     // workspace layout (byte offsets)
     size_t o_xyz, o_atom, o_poff, o_np, o_exps, o_coefs, o_pnat, o_psort, o_prims, o_Q, o_cls, o_work, o_eri,
-        total;
+        o_stage, total;
+    int nslot = 0;            // staging slots for split classes
+    size_t stage_nacc = 0;    // largest split-class accumulator count present
     size_t work_ints = 0;
     char *ws = nullptr;
     bool bound = false;
@@ -291,6 +294,12 @@ int mjk_plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts, m
             p->bps.push_back(bp);
         }
     p->work_ints = woff;
+    // split classes present: staging for one item per persistent block
+    for (const auto &bp : p->bps) {
+        const ClassEntry &ce = kClassTable[bp.qcls];
+        if (ce.split) p->stage_nacc = std::max(p->stage_nacc, (size_t)ce.nacc);
+    }
+    p->nslot = p->stage_nacc ? kSlotsPerCU * std::max(1, ctx->ncu) : 0;
 
     // workspace layout
     size_t off = 0;
@@ -312,6 +321,7 @@ int mjk_plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts, m
     p->o_cls = take(sizeof(int32_t) * p->npair);
     p->o_work = take(sizeof(int32_t) * p->work_ints);
     p->o_eri = take(sizeof(EriItem) * kEriStage);
+    p->o_stage = take(sizeof(double) * 64 * p->stage_nacc * (size_t)p->nslot);
     p->total = off;
 
     p->stats.nbf = p->nbf;
@@ -514,6 +524,8 @@ int mjk_build_jk(mjk_plan *p, const double *D, double *J, double *K, void *strea
         a.chunk_prefix = kc + X.count;
         a.nitems = bp.nitems;
         a.chunk = kChunk;
+        a.stage = (double *)(w + p->o_stage);
+        a.nslot = p->nslot;
         if (p->timing) HIP_TRY(hipEventRecord(p->ev[2 * ib], s));
         if (kClassTable[bp.qcls].jk(a, s)) return fail(MJK_ERR_HIP, "mjk_build_jk: class launch failed");
         if (p->timing) HIP_TRY(hipEventRecord(p->ev[2 * ib + 1], s));

@@ -56,6 +56,8 @@ struct JKLaunch {
     const int32_t *chunk_prefix; // per bra: exclusive prefix of ket chunks (nbra + 1)
     int32_t nitems;            // chunk_prefix[nbra]
     int32_t chunk;             // kets per work item (multiple of 64)
+    double *stage;             // split classes: per-slot staging of [e0|f0]
+    int32_t nslot;             // split classes: staging slots (persistent blocks)
 };
 
 struct EriLaunch {
@@ -81,8 +83,10 @@ using SchwarzFn = int (*)(const SchwarzLaunch &, hipStream_t);
 struct ClassEntry {
     int la, lb, lc, ld;
     int nacc, nout;
-    double vrr_flops;  // per primitive quartet
+    double vrr_flops;  // per primitive quartet (all passes of a split class)
     double hrr_flops;  // per contracted quartet
+    int split;         // 1: multi-pass VRR + cooperative HRR/digestion
+    int npass;
     JKFn jk;
     EriFn eri;
     SchwarzFn schwarz;  // only on diagonal classes (la lb | la lb)

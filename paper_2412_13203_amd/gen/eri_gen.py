@@ -161,12 +161,13 @@ class VRR:
         fs = [t for l in range(self.lc, self.lc + self.ld + 1) for t in cart(l)]
         return es, fs
 
-    def build(self):
+    def build(self, targets=None):
+        """Build the DAG for `targets` (default: every [e0|f0] of the class)."""
         es, fs = self.targets()
+        pairs = [(e, f) for e in es for f in fs] if targets is None else list(targets)
+        self.built_targets = list(pairs)
         # highest angular momentum first: large nodes pull in shared low nodes
-        pairs = [(e, f) for e in es for f in fs]
-        pairs.sort(key=lambda ef: -(sum(ef[0]) + sum(ef[1])))
-        for e, f in pairs:
+        for e, f in sorted(pairs, key=lambda ef: -(sum(ef[0]) + sum(ef[1]))):
             self.need(e, f, 0)
         return es, fs
 
@@ -182,18 +183,105 @@ class VRR:
                 fl += 4
             if "x5" in d:
                 fl += 2
-        es, fs = self.targets()
-        return fl + len(es) * len(fs)
+        return fl + len(self.built_targets)
 
 
-def best_vrr(la, lb, lc, ld):
+LAMBDAS = (0.0, 0.5, 1.0, 2.0, 4.0)
+
+
+def schedule_low_pressure(order):
+    """Reorder a recurrence DAG (topologically sorted node list) to keep few
+    intermediates alive: greedy list scheduling that always emits the ready
+    node freeing the most values (ties: original order).  Returns the new
+    order and its peak number of live intermediates."""
+    nodes = {id(n): n for n in order}
+    users = {k: [] for k in nodes}
+    for n in order:
+        for d in set(id(x) for x in n.deps.values()):
+            if d in nodes:
+                users[d].append(id(n))
+    left = {k: len(u) for k, u in users.items()}
+    ndeps = {id(n): len(set(id(x) for x in n.deps.values() if id(x) in nodes)) for n in order}
+    pos = {id(n): i for i, n in enumerate(order)}
+    ready = [id(n) for n in order if ndeps[id(n)] == 0]
+    out, live, peak = [], set(), 0
+    while ready:
+        best = None
+        for r in ready:
+            n = nodes[r]
+            deps = set(id(x) for x in n.deps.values() if id(x) in nodes)
+            freed = sum(1 for d in deps if left[d] == 1)
+            score = (freed - (1 if left[r] > 0 else 0), -pos[r])
+            if best is None or score > best[0]:
+                best = (score, r)
+        r = best[1]
+        ready.remove(r)
+        n = nodes[r]
+        out.append(n)
+        for d in set(id(x) for x in n.deps.values() if id(x) in nodes):
+            left[d] -= 1
+            if left[d] == 0:
+                live.discard(d)
+        if left[r] > 0:
+            live.add(r)
+        peak = max(peak, len(live))
+        for u in users[r]:
+            ndeps[u] -= 1
+            if ndeps[u] == 0:
+                ready.append(u)
+    assert len(out) == len(order)
+    return out, peak
+
+
+def best_vrr(la, lb, lc, ld, targets=None):
     best = None
-    for lam in (0.0, 0.5, 1.0, 2.0, 4.0):
+    for lam in LAMBDAS:
         v = VRR(la, lb, lc, ld, lam)
-        v.build()
+        v.build(targets)
         key = (v.flops(), len(v.order))
         if best is None or key < best[0]:
             best = (key, v)
+    v = best[1]
+    v.order, v.live_peak = schedule_low_pressure(v.order)
+    return v
+
+
+def _axis_key(t):
+    m = max(t)
+    return (t.index(m), t)
+
+
+def choose_passes(la, lb, lc, ld, max_acc):
+    """Split the [e0|f0] targets into passes of at most max_acc accumulators.
+
+    A pass is a group of ket components f (or bra components e) with every
+    component of the other side; groups follow the dominant Cartesian axis so
+    that the recurrence cones of a pass overlap as much as possible.  The
+    split with the fewest total flops (the cones are recomputed per pass)
+    wins.  Returns a list of target lists."""
+    es = [t for l in range(la, la + lb + 1) for t in cart(l)]
+    fs = [t for l in range(lc, lc + ld + 1) for t in cart(l)]
+    allt = [(e, f) for e in es for f in fs]
+    if len(allt) <= max_acc:
+        return [allt]
+    best = None
+    for side in ("f", "e"):
+        items, other = (fs, es) if side == "f" else (es, fs)
+        per = max_acc // len(other)
+        if per < 1:
+            continue
+        srt = sorted(items, key=_axis_key)
+        ngrp = -(-len(srt) // per)
+        # balanced contiguous groups
+        bounds = [round(g * len(srt) / ngrp) for g in range(ngrp + 1)]
+        groups = [srt[bounds[g]:bounds[g + 1]] for g in range(ngrp)]
+        passes = [[(e, f) for e in es for f in g] if side == "f" else [(e, f) for e in g for f in fs]
+                  for g in groups]
+        tot = sum(best_vrr(la, lb, lc, ld, p).flops() for p in passes)
+        if best is None or tot < best[0]:
+            best = (tot, passes)
+    if best is None:
+        raise ValueError("max_acc too small for this class")
     return best[1]
 
 
@@ -252,8 +340,20 @@ def cls_name(la, lb, lc, ld):
     return f"{s[la]}{s[lb]}{s[lc]}{s[ld]}"
 
 
+# classes whose accumulators exceed this many doubles run as several passes
+MAX_ACC = int(os.environ.get("MJK_MAX_ACC", "96"))
+# a compiler scheduling fence every this many recurrence nodes keeps the
+# low-pressure emission order (0 = no fences)
+SCHED_WINDOW = int(os.environ.get("MJK_SCHED_WINDOW", "0"))
+
+
+def fence(lines, count):
+    if SCHED_WINDOW and count % SCHED_WINDOW == SCHED_WINDOW - 1:
+        lines.append("    __builtin_amdgcn_sched_barrier(0);")
+
+
 class ClassCode:
-    def __init__(self, la, lb, lc, ld):
+    def __init__(self, la, lb, lc, ld, max_acc=MAX_ACC):
         self.la, self.lb, self.lc, self.ld = la, lb, lc, ld
         self.name = cls_name(la, lb, lc, ld)
         self.vrr = best_vrr(la, lb, lc, ld)
@@ -270,6 +370,15 @@ class ClassCode:
         self.bra_first = cost_bra_first <= cost_ket_first
         self.hrr_flops = 2 * min(cost_bra_first, cost_ket_first)
         self.nout = nab * ncd
+        self.nab, self.ncd = nab, ncd
+        self.split = self.nacc > max_acc
+        self.passes = []
+        if self.split:
+            for tg in choose_passes(la, lb, lc, ld, max_acc):
+                self.passes.append((tg, best_vrr(la, lb, lc, ld, tg)))
+            self.split_flops = sum(v.flops() for _, v in self.passes)
+            # cooperative HRR: bra per ket column, then ket per (ab) row
+            self.split_hrr_flops = 2 * (self.hb.count() * nF + nab * self.hk.count())
 
     # ---- VRR ----
     def emit_vrr(self):
@@ -324,6 +433,7 @@ class ClassCode:
             lines.append(f"    const T {n.name} = {expr};")
             if key in targets:
                 lines.append(f"    acc[{targets[key]}] += {n.name};")
+            fence(lines, len(lines))
         # targets that are base nodes ([00|00]^(0) for the (ss|ss) class)
         for key, k in targets.items():
             node = v.nodes[key]
@@ -422,11 +532,133 @@ class ClassCode:
         lines.append("}")
         return "\n".join(lines)
 
+    # ---- split classes: VRR passes and cooperative HRR pieces ----
+    def emit_vrr_pass(self, k):
+        targets, v = self.passes[k]
+        nF = len(self.fs)
+        lines = ["template <typename T>",
+                 f"__device__ __forceinline__ void vrr_{self.name}_p{k}(const T* __restrict__ F, const VrrGeom<T>& g, "
+                 f"T* __restrict__ acc)", "{",
+                 f"    // pass {k}: {len(targets)} of {self.nacc} targets, {len(v.order)} intermediates"]
+        tmap = {(e, f, 0): j for j, (e, f) in enumerate(targets)}
+        consts = {}
+
+        def coef(kind, cnt):
+            key = (kind, cnt)
+            if key not in consts:
+                base = {"p": "g.oo2p", "q": "g.oo2q", "pq": "g.oo2pq"}[kind]
+                if cnt == 1:
+                    consts[key] = base
+                else:
+                    consts[key] = f"c_{kind}{cnt}"
+                    lines.append(f"    const T c_{kind}{cnt} = T({cnt}) * {base};")
+            return consts[key]
+
+        for n in v.order:
+            d = n.deps
+            i = n.axis
+            if n.side == "b":
+                A, W, rr, kind, cnt, ocnt = f"g.PA[{i}]", f"g.WP[{i}]", "g.rho_p", "p", n.e[i] - 1, n.f[i]
+            else:
+                A, W, rr, kind, cnt, ocnt = f"g.QC[{i}]", f"g.WQ[{i}]", "g.rho_q", "q", n.f[i] - 1, n.e[i]
+            expr = f"{A} * {d['x1'].name} + {W} * {d['x2'].name}"
+            if "x3" in d:
+                expr += f" + {coef(kind, cnt)} * ({d['x3'].name} - {rr} * {d['x4'].name})"
+            if "x5" in d:
+                expr += f" + {coef('pq', ocnt)} * {d['x5'].name}"
+            lines.append(f"    const T {n.name} = {expr};")
+            key = (n.e, n.f, n.m)
+            if key in tmap:
+                lines.append(f"    acc[{tmap[key]}] += {n.name};")
+            fence(lines, len(lines))
+        for key, j in tmap.items():
+            if v.nodes[key].side == "":
+                lines.append(f"    acc[{j}] += {v.nodes[key].name};")
+        lines.append("}")
+        gmap = [self.eidx[e] * nF + self.fidx[f] for e, f in targets]
+        lines.append(f"__device__ constexpr int map_{self.name}_p{k}[{len(gmap)}] = {{{', '.join(map(str, gmap))}}};")
+        return "\n".join(lines)
+
+    def emit_hrr_col_row(self):
+        """hrr_bra_col: one ket column f of [e0|f0] (LDS, [e][f]) -> (ab|f] (LDS, [ab][f]);
+        hrr_ket_row: one (ab) row of (ab|f] -> (ab|cd) for every cd (registers)."""
+        la, lb, lc, ld = self.la, self.lb, self.lc, self.ld
+        nb, nd = ncart(lb), ncart(ld)
+        nF = len(self.fs)
+        L = ["template <typename T>",
+             f"__device__ __forceinline__ void hrr_bra_col_{self.name}(const T* __restrict__ ef, int f, const T AB[3], "
+             "T* __restrict__ abf)", "{"]
+        hb = self.hb
+
+        def bname(key):
+            node = hb.nodes[key]
+            if node[0] == "base":
+                return f"ef[{self.eidx[node[1]] * nF} + f]"
+            return f"b{node[6]}"
+
+        for node in hb.order:
+            _, a, b, i, c0, c1, k = node
+            L.append(f"    const T b{k} = {bname(c0)} + AB[{i}] * {bname(c1)};")
+        for a in cart(la):
+            for b in cart(lb):
+                L.append(f"    abf[{(cidx(a) * nb + cidx(b)) * nF} + f] = {bname((a, b))};")
+        L.append("}")
+        L += ["template <typename T>",
+              f"__device__ __forceinline__ void hrr_ket_row_{self.name}(const T* __restrict__ row, const T CD[3], "
+              "T* __restrict__ out)", "{"]
+        hk = self.hk
+
+        def kname(key):
+            node = hk.nodes[key]
+            if node[0] == "base":
+                return f"row[{self.fidx[node[1]]}]"
+            return f"k{node[6]}"
+
+        for node in hk.order:
+            _, c, d, i, c0, c1, k = node
+            L.append(f"    const T k{k} = {kname(c0)} + CD[{i}] * {kname(c1)};")
+        for c in cart(lc):
+            for d in cart(ld):
+                L.append(f"    out[{cidx(c) * nd + cidx(d)}] = {kname((c, d))};")
+        L.append("}")
+        return "\n".join(L)
+
+    def emit_split_trait(self):
+        la, lb, lc, ld = self.la, self.lb, self.lc, self.ld
+        P = len(self.passes)
+        lines = ["template <>", f"struct EriSplit<{la}, {lb}, {lc}, {ld}> {{",
+                 f"    static constexpr int NPASS = {P};",
+                 f"    static constexpr int NE = {len(self.es)};", f"    static constexpr int NF = {len(self.fs)};",
+                 f"    static constexpr int NACC = {self.nacc};",
+                 f"    static constexpr int MAXP = {max(len(t) for t, _ in self.passes)};"]
+        for k, (tg, _) in enumerate(self.passes):
+            lines.append(f"    static constexpr int N{k} = {len(tg)};")
+        lines.append("    template <int P> __device__ static constexpr int npass_acc() {")
+        lines.append("        " + " ".join(f"if constexpr (P == {k}) return {len(tg)};" for k, (tg, _) in enumerate(self.passes))
+                     + " return 0; }")
+        lines.append("    template <int P> __device__ static __forceinline__ int gmap(int j) {")
+        lines.append("        " + " ".join(f"if constexpr (P == {k}) return map_{self.name}_p{k}[j];"
+                                           for k in range(P)) + " return 0; }")
+        lines.append("    template <int P, typename T>")
+        lines.append("    __device__ static __forceinline__ void vrr(const T *F, const VrrGeom<T> &g, T *acc) {")
+        lines.append("        " + " ".join(f"if constexpr (P == {k}) vrr_{self.name}_p{k}<T>(F, g, acc);"
+                                           for k in range(P)) + " }")
+        lines.append("    template <typename T>")
+        lines.append("    __device__ static __forceinline__ void hrr_bra_col(const T *ef, int f, const T AB[3], T *abf)")
+        lines.append(f"    {{ hrr_bra_col_{self.name}<T>(ef, f, AB, abf); }}")
+        lines.append("    template <typename T>")
+        lines.append("    __device__ static __forceinline__ void hrr_ket_row(const T *row, const T CD[3], T *out)")
+        lines.append(f"    {{ hrr_ket_row_{self.name}<T>(row, CD, out); }}")
+        lines.append("};")
+        return "\n".join(lines)
+
     def info(self):
         return {
             "class": self.name, "L": self.vrr.L, "nacc": self.nacc, "nout": self.nout,
             "vrr_nodes": len(self.vrr.order), "vrr_flops": self.vrr.flops(), "vrr_lambda": self.vrr.lam,
             "hrr_flops": self.hrr_flops, "hrr_bra_first": self.bra_first,
+            "split": self.split, "npass": len(self.passes),
+            "split_vrr_flops": self.split_flops if self.split else None,
         }
 
 
@@ -487,13 +719,19 @@ def generate(outdir, lmax=2):
         body.append(cc.emit_vrr())
         body.append(cc.emit_hrr())
         body.append(emit_trait(cc))
+        if cc.split:
+            for k in range(len(cc.passes)):
+                body.append(cc.emit_vrr_pass(k))
+            body.append(cc.emit_hrr_col_row())
+            body.append(cc.emit_split_trait())
         infos.append(cc.info())
     _write(os.path.join(outdir, "eri_classes.inc"), "\n\n".join(body) + "\n")
     tus = []
     for cc in ccs:
         lines = ["// Generated by paper_2412_13203_amd/gen/eri_gen.py -- do not edit.",
                  '#include "../kernels.hpp"', "namespace mjk {",
-                 f"MJK_DEFINE_CLASS({cc.la}, {cc.lb}, {cc.lc}, {cc.ld}, {cc.name})"]
+                 (f"MJK_DEFINE_CLASS_SPLIT({cc.la}, {cc.lb}, {cc.lc}, {cc.ld}, {cc.name})" if cc.split else
+                  f"MJK_DEFINE_CLASS({cc.la}, {cc.lb}, {cc.lc}, {cc.ld}, {cc.name})")]
         if (cc.la, cc.lb) == (cc.lc, cc.ld):
             lines.append(f"MJK_DEFINE_SCHWARZ({cc.la}, {cc.lb}, {cc.name[:2]})")
         lines.append("}  // namespace mjk")
@@ -514,8 +752,12 @@ def generate(outdir, lmax=2):
     d.append("static const ClassEntry kClassTable[kNumQuartetClasses] = {")
     for cc in ccs:
         sch = f"launch_schwarz_{cc.name[:2]}" if (cc.la, cc.lb) == (cc.lc, cc.ld) else "nullptr"
-        d.append(f"    {{{cc.la}, {cc.lb}, {cc.lc}, {cc.ld}, {cc.nacc}, {cc.nout}, {cc.vrr.flops()}, "
-                 f"{cc.hrr_flops}, launch_jk_{cc.name}, launch_eri_{cc.name}, {sch}}},")
+        # algorithmic work: the single-pass recurrence and the cheaper HRR order,
+        # whatever the kernel executes (passes recompute shared intermediates)
+        vfl = cc.vrr.flops()
+        hfl = cc.hrr_flops
+        d.append(f"    {{{cc.la}, {cc.lb}, {cc.lc}, {cc.ld}, {cc.nacc}, {cc.nout}, {vfl}, "
+                 f"{hfl}, {int(cc.split)}, {len(cc.passes)}, launch_jk_{cc.name}, launch_eri_{cc.name}, {sch}}},")
     d.append("};")
     d.append("}  // namespace mjk")
     _write(os.path.join(outdir, "dispatch.inc"), "\n".join(d) + "\n")

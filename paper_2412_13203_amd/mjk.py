@@ -17,7 +17,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libmjk.so")
+# MJK_LIBRARY selects another build of the same library (A/B measurements)
+LIB_PATH = os.environ.get("MJK_LIBRARY") or os.path.join(_HERE, "_lib", "libmjk.so")
 
 MJK_OK = 0
 ERRORS = {-1: "MJK_ERR_INVALID_ARG", -2: "MJK_ERR_UNSUPPORTED", -3: "MJK_ERR_NO_DEVICE", -4: "MJK_ERR_WORKSPACE",
