@@ -63,6 +63,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="also run one device-to-device copy of MB MiB (known-size kernel for scaling "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -79,6 +82,15 @@ def main():
     cfg = inputs.make_config(2)
     b, D_host = cfg["basis"], cfg["D"]
     print(f"bench: workload 40-atom s,s,p,d lattice, nbf={b['nbf']}, tau={cfg['tau']}", file=sys.stderr, flush=True)
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=f"cuda:{dev}")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"bench: calibration copy of {n * 8} bytes done", file=sys.stderr, flush=True)
+        del src, dst
 
     torch.cuda.synchronize()
     t0 = time.time()

@@ -113,18 +113,15 @@ __device__ __forceinline__ PrimPairD load_prim(const PrimPairD *__restrict__ p)
     return *p;
 }
 
-// Contracted [e0|f0] of one shell quartet: loop over its primitive quartets.
-template <int LA, int LB, int LC, int LD>
-__device__ __forceinline__ void contract_quartet(const ShellPairD &bra, const ShellPairD &ket,
-                                                 const PrimPairD *__restrict__ prims, bool active,
-                                                 double *acc)
+
+// Loop over the primitive quartets of one shell quartet, ket primitives
+// outer (each lane loads its own ket record once), bra primitives inner
+// (wave-uniform records: scalar loads).  body(F, g) receives
+// [00|00]^(m) = prefactor * F_m(T), m = 0..L, and the recurrence geometry.
+template <int L, typename Body>
+__device__ __forceinline__ void prim_loop(const ShellPairD &bra, const ShellPairD &ket,
+                                          const PrimPairD *__restrict__ prims, bool active, Body &&body)
 {
-    using C = EriClass<LA, LB, LC, LD>;
-    constexpr int L = LA + LB + LC + LD;
-#pragma unroll
-    for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
-    // ket primitives outer: each lane loads its own ket record once; the bra
-    // records are wave-uniform (scalar loads) in the inner loop
     const int nk = active ? ket.nprim : 0;
     for (int ik = 0; ik < nk; ++ik) {
         const PrimPairD kp = load_prim(prims + ket.prim_off + ik);
@@ -137,9 +134,23 @@ __device__ __forceinline__ void contract_quartet(const ShellPairD &bra, const Sh
             boys_fm<L>(T, F);
 #pragma unroll
             for (int m = 0; m <= L; ++m) F[m] *= pref;
-            C::template vrr<double>(F, g, acc);
+            body(F, g);
         }
     }
+}
+
+// Contracted [e0|f0] of one shell quartet: loop over its primitive quartets.
+template <int LA, int LB, int LC, int LD>
+__device__ __forceinline__ void contract_quartet(const ShellPairD &bra, const ShellPairD &ket,
+                                                 const PrimPairD *__restrict__ prims, bool active,
+                                                 double *acc)
+{
+    using C = EriClass<LA, LB, LC, LD>;
+    constexpr int L = LA + LB + LC + LD;
+#pragma unroll
+    for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
+    prim_loop<L>(bra, ket, prims, active,
+                 [&](const double *F, const VrrGeom<double> &g) { C::template vrr<double>(F, g, acc); });
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -377,21 +388,8 @@ __device__ __forceinline__ void split_pass(const ShellPairD &bra, const ShellPai
     double acc[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) acc[i] = 0.0;
-    const int nk = active ? ket.nprim : 0;
-    for (int ik = 0; ik < nk; ++ik) {
-        const PrimPairD kp = load_prim(prims + ket.prim_off + ik);
-        for (int ib = 0; ib < bra.nprim; ++ib) {
-            const PrimPairD bp = load_prim(prims + bra.prim_off + ib);
-            VrrGeom<double> g;
-            double T;
-            const double pref = prim_geom(bp, kp, g, T);
-            double F[L + 1];
-            boys_fm<L>(T, F);
-#pragma unroll
-            for (int m = 0; m <= L; ++m) F[m] *= pref;
-            S::template vrr<P, double>(F, g, acc);
-        }
-    }
+    prim_loop<L>(bra, ket, prims, active,
+                 [&](const double *F, const VrrGeom<double> &g) { S::template vrr<P, double>(F, g, acc); });
     // The lane offset is made opaque here so that the compiler cannot hoist
     // one 64-bit store address per target out of the item loop (that many
     // live addresses would be spilled to scratch).

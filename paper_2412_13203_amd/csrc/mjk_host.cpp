@@ -21,7 +21,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mjk.h"
+#include "mjk.h"
 #include "gen/dispatch.inc"
 #include "mjk_types.hpp"
 
