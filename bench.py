@@ -57,12 +57,60 @@ def cpu_baseline(cfg, target_s=15.0):
     }
 
 
+def mixed_comparison(torch, mjk, inputs, dev, taus=(1e-4,), steps=2):
+    """120-atom s,s,p,d workload: FP64 path vs mixed path (same plan inputs).
+    E2 = 1/2 Tr(DJ) - 1/4 Tr(DK); the FP64 GPU path is the reference here
+    (it matches the FP64 oracle to ~1e-13 relative on the parity tests)."""
+    cfg = inputs.make_config(3)
+    b = cfg["basis"]
+    D = torch.as_tensor(cfg["D"], device=f"cuda:{dev}")
+    res = {}
+    runs = [("fp64", 0.0)] + [(f"mixed_{t:g}", t) for t in taus]
+    for name, f32 in runs:
+        plan = mjk.Plan(b, tau=cfg["tau"], fp32_tau=f32, device=dev)
+        J = torch.empty_like(D)
+        K = torch.empty_like(D)
+        plan.build_jk(D, J, K)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan.build_jk(D, J, K)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        e2 = float(0.5 * torch.sum(D * J) - 0.25 * torch.sum(D * K))
+        res[name] = {"ms": ms, "e2": e2, "quartets": plan.stats["nquartet_kept"],
+                     "quartets_fp32": plan.stats["nquartet_fp32"], "J": J, "K": K}
+        print(f"bench: 120-atom {name}: {ms:.1f} ms, E2 {e2:.10f}", file=sys.stderr, flush=True)
+        del plan
+    f = res["fp64"]
+    out = {"workload": "120-atom jittered-lattice molecule, s,s,p,d x 3 primitives, nbf 1320, Schwarz 1e-10",
+           "nbf": b["nbf"], "quartets_kept": f["quartets"], "fp64_ms": f["ms"],
+           "fp64_quartets_per_s": f["quartets"] / (f["ms"] * 1e-3), "e2_fp64": f["e2"], "by_fp32_tau": []}
+    for t in taus:
+        m = res[f"mixed_{t:g}"]
+        out["by_fp32_tau"].append({
+            "fp32_tau": t, "quartets_fp32": m["quartets_fp32"], "mixed_ms": m["ms"],
+            "speedup_vs_fp64": f["ms"] / m["ms"], "mixed_quartets_per_s": m["quartets"] / (m["ms"] * 1e-3),
+            "e2_mixed": m["e2"], "e2_abs_err": abs(m["e2"] - f["e2"]),
+            "max_abs_dJ": float(torch.max(torch.abs(m["J"] - f["J"]))),
+            "max_abs_dK": float(torch.max(torch.abs(m["K"] - f["K"])))})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed", action="store_true",
+                    help="also run the 120-atom mixed-precision comparison (FP32 below Q_AB Q_CD = 1e-4) "
+                         "and report its speedup over the FP64 path and its E2 difference")
+    ap.add_argument("--fp32-tau", type=float, nargs="+", default=[1e-4],
+                    help="mixed-precision thresholds for --mixed (first one is the headline)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="also run one device-to-device copy of MB MiB (known-size kernel for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -185,6 +233,8 @@ def main():
         "classes": classes,
         "parity_vs_stored_oracle_blocks": {"max_abs_dJ": dj, "max_abs_dK": dk},
     }
+    if args.mixed:
+        out["mixed"] = mixed_comparison(torch, mjk, inputs, dev, taus=args.fp32_tau)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)

@@ -77,7 +77,11 @@ typedef struct mjk_basis {
  * schwarz_tau: a unique shell quartet (AB|CD) is skipped iff
  *   Q_AB * Q_CD < schwarz_tau, with Q_AB = sqrt(max_{a in A, b in B} (ab|ab))
  *   (Cauchy-Schwarz bound; 0 keeps every quartet).
- * fp32_tau: reserved for the mixed-precision form; must be 0 here. */
+ * fp32_tau: mixed precision.  A kept quartet with Q_AB * Q_CD < fp32_tau
+ *   runs its vertical recurrence and its contraction over primitives in FP32
+ *   (the geometry and Boys function are evaluated in FP64 and rounded); the
+ *   horizontal recurrence and the digestion into J and K run in FP64.
+ *   0 = every quartet in FP64. */
 typedef struct mjk_jk_opts {
     double schwarz_tau;
     double fp32_tau;
@@ -92,6 +96,7 @@ typedef struct mjk_plan_stats {
     int64_t nprim_pair;         /* primitive pairs over all shell pairs            */
     int64_t nquartet_total;     /* unique shell quartets before screening          */
     int64_t nquartet_kept;      /* unique shell quartets after screening           */
+    int64_t nquartet_fp32;      /* kept quartets run in FP32 (fp32_tau)            */
     int64_t nprim_quartet_kept; /* primitive quartets of the kept quartets         */
     int64_t ncart_eri_kept;     /* Cartesian integrals of the kept quartets        */
     int64_t nlaunch;            /* kernel launches per mjk_build_jk                */

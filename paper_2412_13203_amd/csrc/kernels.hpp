@@ -140,17 +140,45 @@ __device__ __forceinline__ void prim_loop(const ShellPairD &bra, const ShellPair
 }
 
 // Contracted [e0|f0] of one shell quartet: loop over its primitive quartets.
-template <int LA, int LB, int LC, int LD>
+// Hand the recurrence its inputs in the accumulation type T: for T = float
+// the geometry and Boys values (computed in FP64) are rounded to FP32 here.
+template <typename T>
+__device__ __forceinline__ void to_type(const VrrGeom<double> &g, VrrGeom<T> &h)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        h.PA[i] = (T)g.PA[i];
+        h.WP[i] = (T)g.WP[i];
+        h.QC[i] = (T)g.QC[i];
+        h.WQ[i] = (T)g.WQ[i];
+    }
+    h.oo2p = (T)g.oo2p;
+    h.oo2q = (T)g.oo2q;
+    h.oo2pq = (T)g.oo2pq;
+    h.rho_p = (T)g.rho_p;
+    h.rho_q = (T)g.rho_q;
+}
+
+template <int LA, int LB, int LC, int LD, typename T>
 __device__ __forceinline__ void contract_quartet(const ShellPairD &bra, const ShellPairD &ket,
-                                                 const PrimPairD *__restrict__ prims, bool active,
-                                                 double *acc)
+                                                 const PrimPairD *__restrict__ prims, bool active, T *acc)
 {
     using C = EriClass<LA, LB, LC, LD>;
     constexpr int L = LA + LB + LC + LD;
 #pragma unroll
-    for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
-    prim_loop<L>(bra, ket, prims, active,
-                 [&](const double *F, const VrrGeom<double> &g) { C::template vrr<double>(F, g, acc); });
+    for (int i = 0; i < C::NACC; ++i) acc[i] = T(0);
+    prim_loop<L>(bra, ket, prims, active, [&](const double *F, const VrrGeom<double> &g) {
+        if constexpr (sizeof(T) == sizeof(double)) {
+            C::template vrr<double>(F, g, acc);
+        } else {
+            T Ft[L + 1];
+#pragma unroll
+            for (int m = 0; m <= L; ++m) Ft[m] = (T)F[m];
+            VrrGeom<T> h;
+            to_type(g, h);
+            C::template vrr<T>(Ft, h, acc);
+        }
+    });
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -169,7 +197,7 @@ __device__ __forceinline__ double wave_sum(double v)
 // J = Jt + Jt^T and K = Kt + Kt^T afterwards (k_symmetrize).  Jt_ab is
 // bra-uniform, so it is reduced across the wave before its atomic.
 // ---------------------------------------------------------------------------
-template <int LA, int LB, int LC, int LD>
+template <int LA, int LB, int LC, int LD, typename T>
 __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
 {
     using C = EriClass<LA, LB, LC, LD>;
@@ -186,8 +214,8 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
             hi = mid;
     }
     const int b = lo;
-    const int kbeg = (item - a.chunk_prefix[b]) * a.chunk;
-    const int kend = min(kbeg + a.chunk, a.ket_count[b]);
+    const int kbeg = a.ket_start[b] + (item - a.chunk_prefix[b]) * a.chunk;
+    const int kend = min(kbeg + a.chunk, a.ket_end[b]);
     const int bra_pos = a.bra_begin + b;
     const ShellPairD bra = a.pairs[bra_pos];
     const int N = a.nbf;
@@ -207,10 +235,19 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
         const bool active = k < kend;
         const int ket_pos = a.ket_begin + (active ? k : kbeg);
         const ShellPairD ket = a.pairs[ket_pos];
-        double acc[C::NACC];
-        contract_quartet<LA, LB, LC, LD>(bra, ket, a.prims, active, acc);
+        T acc[C::NACC];
+        contract_quartet<LA, LB, LC, LD, T>(bra, ket, a.prims, active, acc);
         double eri[C::NOUT];
-        C::template hrr<double>(acc, bra.AB, ket.AB, eri);
+        if constexpr (sizeof(T) == sizeof(double)) {
+            C::template hrr<double>(acc, bra.AB, ket.AB, eri);
+        } else {
+            // FP32 recurrence and contraction; the horizontal recurrence (whose
+            // AB, CD factors amplify rounding) runs on the widened values
+            double acc64[C::NACC];
+#pragma unroll
+            for (int i = 0; i < C::NACC; ++i) acc64[i] = (double)acc[i];
+            C::template hrr<double>(acc64, bra.AB, ket.AB, eri);
+        }
 
         double s = 1.0;
         if (bra.same) s *= 2.0;
@@ -316,7 +353,7 @@ __global__ __launch_bounds__(64) void k_eri(EriLaunch a)
     const ShellPairD bra = a.pairs[it.bra];
     const ShellPairD ket = a.pairs[it.ket];
     double acc[C::NACC];
-    contract_quartet<LA, LB, LC, LD>(bra, ket, a.prims, true, acc);
+    contract_quartet<LA, LB, LC, LD, double>(bra, ket, a.prims, true, acc);
     double eri[C::NOUT];
     C::template hrr<double>(acc, bra.AB, ket.AB, eri);
     const bool sab = it.flags & 1, scd = it.flags & 2, sbk = it.flags & 4;
@@ -355,7 +392,7 @@ __global__ __launch_bounds__(64) void k_schwarz(SchwarzLaunch a)
     const int pi = a.idx[t];
     const ShellPairD pr = a.pairs[pi];
     double acc[C::NACC];
-    contract_quartet<LA, LB, LA, LB>(pr, pr, a.prims, true, acc);
+    contract_quartet<LA, LB, LA, LB, double>(pr, pr, a.prims, true, acc);
     double eri[C::NOUT];
     C::template hrr<double>(acc, pr.AB, pr.AB, eri);
     double mx = 0.0;
@@ -377,7 +414,7 @@ __global__ __launch_bounds__(64) void k_schwarz(SchwarzLaunch a)
 //            lane, with the bra-uniform Jt_ab kept per lane across the item.
 // Blocks are persistent (grid = staging slots) and stride over the items.
 // ---------------------------------------------------------------------------
-template <int LA, int LB, int LC, int LD, int P>
+template <int LA, int LB, int LC, int LD, int P, typename T>
 __device__ __forceinline__ void split_pass(const ShellPairD &bra, const ShellPairD &ket,
                                            const PrimPairD *__restrict__ prims, bool active,
                                            double *__restrict__ stage, int lane)
@@ -385,11 +422,21 @@ __device__ __forceinline__ void split_pass(const ShellPairD &bra, const ShellPai
     using S = EriSplit<LA, LB, LC, LD>;
     constexpr int L = LA + LB + LC + LD;
     constexpr int NP = S::template npass_acc<P>();
-    double acc[NP];
+    T acc[NP];
 #pragma unroll
-    for (int i = 0; i < NP; ++i) acc[i] = 0.0;
-    prim_loop<L>(bra, ket, prims, active,
-                 [&](const double *F, const VrrGeom<double> &g) { S::template vrr<P, double>(F, g, acc); });
+    for (int i = 0; i < NP; ++i) acc[i] = T(0);
+    prim_loop<L>(bra, ket, prims, active, [&](const double *F, const VrrGeom<double> &g) {
+        if constexpr (sizeof(T) == sizeof(double)) {
+            S::template vrr<P, double>(F, g, acc);
+        } else {
+            T Ft[L + 1];
+#pragma unroll
+            for (int m = 0; m <= L; ++m) Ft[m] = (T)F[m];
+            VrrGeom<T> h;
+            to_type(g, h);
+            S::template vrr<P, T>(Ft, h, acc);
+        }
+    });
     // The lane offset is made opaque here so that the compiler cannot hoist
     // one 64-bit store address per target out of the item loop (that many
     // live addresses would be spilled to scratch).
@@ -397,21 +444,23 @@ __device__ __forceinline__ void split_pass(const ShellPairD &bra, const ShellPai
     __asm__ volatile("" : "+v"(off));
     double *sl = stage + off;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) sl[S::template gmap<P>(j) * 64] = acc[j];
+    for (int j = 0; j < NP; ++j) sl[S::template gmap<P>(j) * 64] = (double)acc[j];
 }
 
-template <int LA, int LB, int LC, int LD, int P>
+template <int LA, int LB, int LC, int LD, int P, typename T>
 __device__ __forceinline__ void split_passes(const ShellPairD &bra, const ShellPairD &ket,
                                              const PrimPairD *__restrict__ prims, bool active,
                                              double *__restrict__ stage, int lane)
 {
     if constexpr (P < EriSplit<LA, LB, LC, LD>::NPASS) {
-        split_pass<LA, LB, LC, LD, P>(bra, ket, prims, active, stage, lane);
-        split_passes<LA, LB, LC, LD, P + 1>(bra, ket, prims, active, stage, lane);
+        split_pass<LA, LB, LC, LD, P, T>(bra, ket, prims, active, stage, lane);
+        split_passes<LA, LB, LC, LD, P + 1, T>(bra, ket, prims, active, stage, lane);
     }
 }
 
-template <int LA, int LB, int LC, int LD>
+// T = float: the passes run the recurrence and the contraction in FP32 and
+// stage the contracted values as FP64; HRR and digestion are FP64.
+template <int LA, int LB, int LC, int LD, typename T>
 __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
 {
     using S = EriSplit<LA, LB, LC, LD>;
@@ -439,8 +488,8 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
                 hi = mid;
         }
         const int b = lo;
-        const int kbeg = (item - a.chunk_prefix[b]) * a.chunk;
-        const int kend = min(kbeg + a.chunk, a.ket_count[b]);
+        const int kbeg = a.ket_start[b] + (item - a.chunk_prefix[b]) * a.chunk;
+        const int kend = min(kbeg + a.chunk, a.ket_end[b]);
         const int nact = min(kend - kbeg, 64);
         const int bra_pos = a.bra_begin + b;
         const ShellPairD bra = a.pairs[bra_pos];
@@ -450,7 +499,7 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
         const bool active = lane < nact;
         const int ket_pos = a.ket_begin + (active ? k : kbeg);
         const ShellPairD ket = a.pairs[ket_pos];
-        split_passes<LA, LB, LC, LD, 0>(bra, ket, a.prims, active, stage, lane);
+        split_passes<LA, LB, LC, LD, 0, T>(bra, ket, a.prims, active, stage, lane);
         {
             double s = 1.0;
             if (bra.same) s *= 2.0;
@@ -547,26 +596,45 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
     }
 }
 
+template <int LA, int LB, int LC, int LD, typename T>
+int launch_split(const JKLaunch &a, hipStream_t s)
+{
+    if (a.nitems <= 0) return 0;
+    static int per_cu = -1;
+    static int ncu = 0;
+    if (per_cu < 0) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_jk_split<LA, LB, LC, LD, T>, 64, 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+    }
+    int grid = per_cu * ncu;
+    if (grid > a.nslot) grid = a.nslot;
+    if (grid > a.nitems) grid = a.nitems;
+    if (grid < 1) return -1;
+    hipLaunchKernelGGL((k_jk_split<LA, LB, LC, LD, T>), dim3(grid), dim3(64), 0, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int LA, int LB, int LC, int LD, typename T>
+int launch_plain(const JKLaunch &a, hipStream_t s)
+{
+    if (a.nitems <= 0) return 0;
+    hipLaunchKernelGGL((k_jk<LA, LB, LC, LD, T>), dim3(a.nitems), dim3(64), 0, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 #define MJK_DEFINE_CLASS_SPLIT(LA, LB, LC, LD, NAME)                                                \
     int launch_jk_##NAME(const JKLaunch &a, hipStream_t s)                                         \
     {                                                                                               \
-        if (a.nitems <= 0) return 0;                                                                \
-        static int per_cu = -1;                                                                     \
-        static int ncu = 0;                                                                         \
-        if (per_cu < 0) {                                                                           \
-            int dev = 0;                                                                            \
-            hipGetDevice(&dev);                                                                     \
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);                \
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_jk_split<LA, LB, LC, LD>, 64, \
-                                                             0) != hipSuccess || per_cu < 1)        \
-                per_cu = 1;                                                                         \
-        }                                                                                           \
-        int grid = per_cu * ncu;                                                                    \
-        if (grid > a.nslot) grid = a.nslot;                                                         \
-        if (grid > a.nitems) grid = a.nitems;                                                       \
-        if (grid < 1) return -1;                                                                    \
-        hipLaunchKernelGGL((k_jk_split<LA, LB, LC, LD>), dim3(grid), dim3(64), 0, s, a);            \
-        return hipGetLastError() == hipSuccess ? 0 : -1;                                            \
+        return launch_split<LA, LB, LC, LD, double>(a, s);                                          \
+    }                                                                                               \
+    int launch_jk32_##NAME(const JKLaunch &a, hipStream_t s)                                       \
+    {                                                                                               \
+        return launch_split<LA, LB, LC, LD, float>(a, s);                                           \
     }                                                                                               \
     int launch_eri_##NAME(const EriLaunch &a, hipStream_t s)                                       \
     {                                                                                               \
@@ -578,9 +646,11 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
 #define MJK_DEFINE_CLASS(LA, LB, LC, LD, NAME)                                                      \
     int launch_jk_##NAME(const JKLaunch &a, hipStream_t s)                                         \
     {                                                                                               \
-        if (a.nitems <= 0) return 0;                                                                \
-        hipLaunchKernelGGL((k_jk<LA, LB, LC, LD>), dim3(a.nitems), dim3(64), 0, s, a);              \
-        return hipGetLastError() == hipSuccess ? 0 : -1;                                            \
+        return launch_plain<LA, LB, LC, LD, double>(a, s);                                          \
+    }                                                                                               \
+    int launch_jk32_##NAME(const JKLaunch &a, hipStream_t s)                                       \
+    {                                                                                               \
+        return launch_plain<LA, LB, LC, LD, float>(a, s);                                           \
     }                                                                                               \
     int launch_eri_##NAME(const EriLaunch &a, hipStream_t s)                                       \
     {                                                                                               \

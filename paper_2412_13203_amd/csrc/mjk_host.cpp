@@ -85,7 +85,14 @@ struct Bin {
 struct BinPair {
     int X, Y;          // bin indices, X >= Y in (class, bucket) order
     int qcls;          // quartet class index
-    size_t off;        // int offset in the work-list region: ket_count[nbra], chunk_prefix[nbra+1]
+};
+
+// One launch: the FP64 or the FP32 part of one bin pair's quartets.
+struct WorkList {
+    int bp;            // bin pair
+    int fp32;          // 1: FP32 recurrence (Q_AB Q_CD < fp32_tau)
+    size_t off;        // int offset in the work-list region:
+                       //   ket_start[nbra], ket_end[nbra], chunk_prefix[nbra + 1]
     int nitems;
     int64_t nq;        // kept quartets
     int64_t npq;       // kept primitive quartets
@@ -120,6 +127,7 @@ struct mjk_plan {
     std::vector<int32_t> sorted;         // sorted position -> natural index
     std::vector<Bin> bins;
     std::vector<BinPair> bps;
+    std::vector<WorkList> lists;
     std::vector<std::vector<int32_t>> class_pairs;  // natural indices per pair class
     // workspace layout (byte offsets)
     size_t o_xyz, o_atom, o_poff, o_np, o_exps, o_coefs, o_pnat, o_psort, o_prims, o_Q, o_cls, o_work, o_eri,
@@ -218,8 +226,8 @@ int mjk_plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts, m
     if (opts) o = *opts;
     if (!(std::isfinite(o.schwarz_tau) && o.schwarz_tau >= 0.0))
         return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: schwarz_tau = %g", o.schwarz_tau);
-    if (o.fp32_tau != 0.0)
-        return fail(MJK_ERR_UNSUPPORTED, "mjk_plan_create: fp32_tau must be 0 in this build");
+    if (!(std::isfinite(o.fp32_tau) && o.fp32_tau >= 0.0))
+        return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: fp32_tau = %g", o.fp32_tau);
     if (o.flags & ~MJK_FLAG_CHECK) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: unknown flags 0x%x", o.flags);
 
     auto *p = new mjk_plan;
@@ -289,8 +297,14 @@ int mjk_plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts, m
             bp.X = X;
             bp.Y = Y;
             bp.qcls = quartet_class(p->bins[X].cls, p->bins[Y].cls);
-            bp.off = woff;
-            woff += 2 * (size_t)p->bins[X].count + 1;
+            for (int prec = 0; prec < 2; ++prec) {
+                WorkList wl{};
+                wl.bp = (int)p->bps.size();
+                wl.fp32 = prec;
+                wl.off = woff;
+                woff += 3 * (size_t)p->bins[X].count + 1;
+                p->lists.push_back(wl);
+            }
             p->bps.push_back(bp);
         }
     p->work_ints = woff;
@@ -405,57 +419,79 @@ int mjk_plan_bind(mjk_plan *p, void *workspace, size_t bytes, void *stream)
     for (int k = 0; k < p->npair; ++k) psort[k] = p->pairs_nat[p->sorted[k]];
     HIP_TRY(hipMemcpyAsync(w + p->o_psort, psort.data(), sizeof(ShellPairD) * p->npair, hipMemcpyHostToDevice, s));
 
-    // stage 2: per bin pair, per bra, the kept ket prefix and its chunks
-    const double tau = p->opts.schwarz_tau;
+    // stage 2: per bin pair, per bra, the kept ket prefix of the ket bin
+    // (Q_AB Q_CD >= schwarz_tau), split into its FP64 prefix
+    // (Q_AB Q_CD >= fp32_tau) and FP32 remainder, each cut into chunks
+    const double tau = p->opts.schwarz_tau, tau32 = p->opts.fp32_tau;
     std::vector<int32_t> work(p->work_ints, 0);
-    int64_t nq_kept = 0, nprimq = 0, ncart = 0;
+    int64_t nq_kept = 0, nprimq = 0, ncart = 0, nq32 = 0;
     double flops = 0.0;
     int nlaunch = 0;
-    for (auto &bp : p->bps) {
+    auto prefix_len = [&](const Bin &Y, double qb, double thr) {
+        int lo = 0, hi = Y.count;  // first k with qb * Q_k < thr
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (qb * psort[Y.begin + mid].Q < thr)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        return lo;
+    };
+    for (size_t il = 0; il < p->lists.size(); il += 2) {
+        WorkList &l64 = p->lists[il], &l32 = p->lists[il + 1];
+        const BinPair &bp = p->bps[l64.bp];
         const Bin &X = p->bins[bp.X], &Y = p->bins[bp.Y];
         const ClassEntry &ce = kClassTable[bp.qcls];
-        int32_t *kc = work.data() + bp.off;
-        int32_t *pref = kc + X.count;
-        pref[0] = 0;
-        int64_t nq = 0, npq = 0;
+        int32_t *s64 = work.data() + l64.off, *e64 = s64 + X.count, *p64 = e64 + X.count;
+        int32_t *s32 = work.data() + l32.off, *e32 = s32 + X.count, *p32 = e32 + X.count;
+        p64[0] = p32[0] = 0;
         std::vector<int64_t> ynp(Y.count + 1, 0);  // prefix of K_C K_D over the ket bin
         for (int k = 0; k < Y.count; ++k) ynp[k + 1] = ynp[k] + psort[Y.begin + k].nprim;
+        int64_t q64 = 0, q32 = 0, pq64 = 0, pq32 = 0;
         for (int b = 0; b < X.count; ++b) {
             const double qb = psort[X.begin + b].Q;
-            // kets k of Y kept iff qb * Q_k >= tau; Q_k descending => a prefix
-            int lo = 0, hi = Y.count;  // first k with qb*Q_k < tau
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (qb * psort[Y.begin + mid].Q < tau)
-                    hi = mid;
-                else
-                    lo = mid + 1;
-            }
-            int cnt = lo;
-            if (bp.X == bp.Y) cnt = std::min(cnt, b + 1);
-            kc[b] = cnt;
-            pref[b + 1] = pref[b] + (cnt + kChunk - 1) / kChunk;
-            nq += cnt;
-            npq += (int64_t)psort[X.begin + b].nprim * ynp[cnt];
+            int keep = prefix_len(Y, qb, tau);
+            if (bp.X == bp.Y) keep = std::min(keep, b + 1);
+            int c64 = tau32 > 0.0 ? std::min(keep, prefix_len(Y, qb, tau32)) : keep;
+            s64[b] = 0;
+            e64[b] = c64;
+            s32[b] = c64;
+            e32[b] = keep;
+            p64[b + 1] = p64[b] + (c64 + kChunk - 1) / kChunk;
+            p32[b + 1] = p32[b] + (keep - c64 + kChunk - 1) / kChunk;
+            const int64_t nb = psort[X.begin + b].nprim;
+            q64 += c64;
+            q32 += keep - c64;
+            pq64 += nb * ynp[c64];
+            pq32 += nb * (ynp[keep] - ynp[c64]);
         }
-        bp.nitems = pref[X.count];
-        bp.nq = nq;
         const int nout = ncart_h(ce.la) * ncart_h(ce.lb) * ncart_h(ce.lc) * ncart_h(ce.ld);
         const int L = ce.la + ce.lb + ce.lc + ce.ld;
-        bp.npq = npq;
-        bp.cost = (double)npq * (ce.vrr_flops + prim_overhead_flops(L)) + (double)nq * (ce.hrr_flops + 12.0 * nout);
-        nq_kept += nq;
-        nprimq += npq;
-        ncart += nq * nout;
-        flops += bp.cost;
-        if (bp.nitems > 0) ++nlaunch;
+        const double fpq = ce.vrr_flops + prim_overhead_flops(L), fq = ce.hrr_flops + 12.0 * nout;
+        l64.nitems = p64[X.count];
+        l64.nq = q64;
+        l64.npq = pq64;
+        l64.cost = (double)pq64 * fpq + (double)q64 * fq;
+        l32.nitems = p32[X.count];
+        l32.nq = q32;
+        l32.npq = pq32;
+        l32.cost = (double)pq32 * fpq + (double)q32 * fq;
+        nq_kept += q64 + q32;
+        nq32 += q32;
+        nprimq += pq64 + pq32;
+        ncart += (q64 + q32) * nout;
+        flops += l64.cost + l32.cost;
+        nlaunch += (l64.nitems > 0) + (l32.nitems > 0);
     }
     if (!work.empty())
         HIP_TRY(hipMemcpyAsync(w + p->o_work, work.data(), sizeof(int32_t) * work.size(), hipMemcpyHostToDevice, s));
-    // costliest blocks first
-    std::stable_sort(p->bps.begin(), p->bps.end(), [](const BinPair &a, const BinPair &b) { return a.cost > b.cost; });
+    // costliest launches first
+    std::stable_sort(p->lists.begin(), p->lists.end(),
+                     [](const WorkList &a, const WorkList &b) { return a.cost > b.cost; });
     HIP_TRY(hipStreamSynchronize(s));  // host vectors above are released on return
     p->stats.nquartet_kept = nq_kept;
+    p->stats.nquartet_fp32 = nq32;
     p->stats.nprim_quartet_kept = nprimq;
     p->stats.ncart_eri_kept = ncart;
     p->stats.vrr_flops_kept = flops;
@@ -498,17 +534,18 @@ int mjk_build_jk(mjk_plan *p, const double *D, double *J, double *K, void *strea
     if (launch_fill(J, n2, 0.0, s) || launch_fill(K, n2, 0.0, s))
         return fail(MJK_ERR_HIP, "mjk_build_jk: fill launch failed");
     char *w = p->ws;
-    if (p->timing && p->ev.size() != 2 * p->bps.size()) {
+    if (p->timing && p->ev.size() != 2 * p->lists.size()) {
         for (auto e : p->ev) hipEventDestroy(e);
-        p->ev.assign(2 * p->bps.size(), nullptr);
+        p->ev.assign(2 * p->lists.size(), nullptr);
         for (auto &e : p->ev) HIP_TRY(hipEventCreate(&e));
     }
     p->timed_last = p->timing;
-    for (size_t ib = 0; ib < p->bps.size(); ++ib) {
-        const auto &bp = p->bps[ib];
-        if (bp.nitems <= 0) continue;
+    for (size_t il = 0; il < p->lists.size(); ++il) {
+        const WorkList &wl = p->lists[il];
+        if (wl.nitems <= 0) continue;
+        const BinPair &bp = p->bps[wl.bp];
         const Bin &X = p->bins[bp.X], &Y = p->bins[bp.Y];
-        const int32_t *kc = (const int32_t *)(w + p->o_work) + bp.off;
+        const int32_t *wk = (const int32_t *)(w + p->o_work) + wl.off;
         JKLaunch a{};
         a.pairs = (const ShellPairD *)(w + p->o_psort);
         a.prims = (const PrimPairD *)(w + p->o_prims);
@@ -520,15 +557,17 @@ int mjk_build_jk(mjk_plan *p, const double *D, double *J, double *K, void *strea
         a.nbra = X.count;
         a.ket_begin = Y.begin;
         a.same_bin = bp.X == bp.Y;
-        a.ket_count = kc;
-        a.chunk_prefix = kc + X.count;
-        a.nitems = bp.nitems;
+        a.ket_start = wk;
+        a.ket_end = wk + X.count;
+        a.chunk_prefix = wk + 2 * X.count;
+        a.nitems = wl.nitems;
         a.chunk = kChunk;
         a.stage = (double *)(w + p->o_stage);
         a.nslot = p->nslot;
-        if (p->timing) HIP_TRY(hipEventRecord(p->ev[2 * ib], s));
-        if (kClassTable[bp.qcls].jk(a, s)) return fail(MJK_ERR_HIP, "mjk_build_jk: class launch failed");
-        if (p->timing) HIP_TRY(hipEventRecord(p->ev[2 * ib + 1], s));
+        const ClassEntry &ce = kClassTable[bp.qcls];
+        if (p->timing) HIP_TRY(hipEventRecord(p->ev[2 * il], s));
+        if ((wl.fp32 ? ce.jk32 : ce.jk)(a, s)) return fail(MJK_ERR_HIP, "mjk_build_jk: class launch failed");
+        if (p->timing) HIP_TRY(hipEventRecord(p->ev[2 * il + 1], s));
     }
     if (launch_symmetrize(J, p->nbf, s) || launch_symmetrize(K, p->nbf, s))
         return fail(MJK_ERR_HIP, "mjk_build_jk: symmetrize launch failed");
@@ -618,7 +657,7 @@ int mjk_plan_set_timing(mjk_plan *p, int enable)
 int mjk_plan_timings(mjk_plan *p, mjk_class_timing *out, int32_t cap, int32_t *n)
 {
     if (!p || !n || (cap > 0 && !out)) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_timings: NULL argument");
-    if (!p->timed_last || p->ev.size() != 2 * p->bps.size())
+    if (!p->timed_last || p->ev.size() != 2 * p->lists.size())
         return fail(MJK_ERR_STATE, "mjk_plan_timings: the last build ran without timing");
     std::vector<mjk_class_timing> acc(kNumQuartetClasses);
     for (int q = 0; q < kNumQuartetClasses; ++q) {
@@ -628,17 +667,17 @@ int mjk_plan_timings(mjk_plan *p, mjk_class_timing *out, int32_t cap, int32_t *n
         acc[q].lc = kClassTable[q].lc;
         acc[q].ld = kClassTable[q].ld;
     }
-    for (size_t ib = 0; ib < p->bps.size(); ++ib) {
-        const auto &bp = p->bps[ib];
-        if (bp.nitems <= 0) continue;
+    for (size_t il = 0; il < p->lists.size(); ++il) {
+        const auto &wl = p->lists[il];
+        if (wl.nitems <= 0) continue;
         float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, p->ev[2 * ib], p->ev[2 * ib + 1]));
-        auto &t = acc[bp.qcls];
+        HIP_TRY(hipEventElapsedTime(&ms, p->ev[2 * il], p->ev[2 * il + 1]));
+        auto &t = acc[p->bps[wl.bp].qcls];
         t.nlaunch += 1;
         t.ms += ms;
-        t.nquartet += bp.nq;
-        t.nprim_quartet += bp.npq;
-        t.flops += bp.cost;
+        t.nquartet += wl.nq;
+        t.nprim_quartet += wl.npq;
+        t.flops += wl.cost;
     }
     int k = 0;
     for (int q = 0; q < kNumQuartetClasses; ++q)

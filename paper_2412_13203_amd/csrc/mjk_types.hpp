@@ -52,7 +52,8 @@ struct JKLaunch {
     int32_t nbf;
     int32_t bra_begin, nbra, ket_begin;
     int32_t same_bin;          // bra and ket bins coincide: keep ket <= bra
-    const int32_t *ket_count;  // per bra: number of kets kept (a prefix of the bin)
+    const int32_t *ket_start;  // per bra: first ket (bin position) of this list
+    const int32_t *ket_end;    // per bra: one past the last ket of this list
     const int32_t *chunk_prefix; // per bra: exclusive prefix of ket chunks (nbra + 1)
     int32_t nitems;            // chunk_prefix[nbra]
     int32_t chunk;             // kets per work item (multiple of 64)
@@ -88,6 +89,7 @@ struct ClassEntry {
     int split;         // 1: multi-pass VRR + cooperative HRR/digestion
     int npass;
     JKFn jk;
+    JKFn jk32;         // FP32 recurrence / contraction, FP64 digestion
     EriFn eri;
     SchwarzFn schwarz;  // only on diagonal classes (la lb | la lb)
 };

@@ -242,7 +242,8 @@ def best_vrr(la, lb, lc, ld, targets=None):
         if best is None or key < best[0]:
             best = (key, v)
     v = best[1]
-    v.order, v.live_peak = schedule_low_pressure(v.order)
+    if os.environ.get("MJK_NO_SCHED") != "1":
+        v.order, v.live_peak = schedule_low_pressure(v.order)
     return v
 
 
@@ -743,6 +744,7 @@ def generate(outdir, lmax=2):
          '#include "../mjk_types.hpp"', "namespace mjk {"]
     for cc in ccs:
         d.append(f"int launch_jk_{cc.name}(const JKLaunch &, hipStream_t);")
+        d.append(f"int launch_jk32_{cc.name}(const JKLaunch &, hipStream_t);")
         d.append(f"int launch_eri_{cc.name}(const EriLaunch &, hipStream_t);")
         if (cc.la, cc.lb) == (cc.lc, cc.ld):
             d.append(f"int launch_schwarz_{cc.name[:2]}(const SchwarzLaunch &, hipStream_t);")
@@ -757,7 +759,8 @@ def generate(outdir, lmax=2):
         vfl = cc.vrr.flops()
         hfl = cc.hrr_flops
         d.append(f"    {{{cc.la}, {cc.lb}, {cc.lc}, {cc.ld}, {cc.nacc}, {cc.nout}, {vfl}, "
-                 f"{hfl}, {int(cc.split)}, {len(cc.passes)}, launch_jk_{cc.name}, launch_eri_{cc.name}, {sch}}},")
+                 f"{hfl}, {int(cc.split)}, {len(cc.passes)}, launch_jk_{cc.name}, launch_jk32_{cc.name}, "
+                 f"launch_eri_{cc.name}, {sch}}},")
     d.append("};")
     d.append("}  // namespace mjk")
     _write(os.path.join(outdir, "dispatch.inc"), "\n".join(d) + "\n")

@@ -55,6 +55,7 @@ class PlanStats(ctypes.Structure):
     _fields_ = [
         ("nbf", ctypes.c_int64), ("nshell", ctypes.c_int64), ("npair", ctypes.c_int64),
         ("nprim_pair", ctypes.c_int64), ("nquartet_total", ctypes.c_int64), ("nquartet_kept", ctypes.c_int64),
+        ("nquartet_fp32", ctypes.c_int64),
         ("nprim_quartet_kept", ctypes.c_int64), ("ncart_eri_kept", ctypes.c_int64), ("nlaunch", ctypes.c_int64),
         ("vrr_flops_kept", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t),
     ]
@@ -159,14 +160,14 @@ def _stream(torch, device):
 class Plan:
     """A bound plan: tables for one basis/geometry in a torch-owned workspace."""
 
-    def __init__(self, basis: dict, tau: float = 0.0, flags: int = 0, device: int = 0):
+    def __init__(self, basis: dict, tau: float = 0.0, flags: int = 0, device: int = 0, fp32_tau: float = 0.0):
         import torch
         self.torch = torch
         self.device = device
         self.basis = basis
         self._hb = _HostBasis(basis)
         ctx = context(device)
-        opts = JKOpts(float(tau), 0.0, int(flags))
+        opts = JKOpts(float(tau), float(fp32_tau), int(flags))
         p = ctypes.c_void_p()
         nbytes = ctypes.c_size_t(0)
         _check(lib().mjk_plan_create(ctx, ctypes.byref(self._hb.s), ctypes.byref(opts), ctypes.byref(p),
