@@ -1,6 +1,6 @@
 """Benchmark: J/K build throughput (unique shell quartets / s) on one MI355X.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline] [--no-mixed] [--no-grad]
 
 Workload: 40 atoms on a jittered cubic lattice (2.5 bohr, +-0.3), shells
 s, s, p, d per atom with 3 primitives each (440 Cartesian functions), Schwarz
@@ -12,6 +12,9 @@ work lists) is built once before timing and reported separately as plan_ms.
 Prints one JSON line.  `roofline` is for the costliest class kernel, timed
 with HIP events on the launch stream during the timed steps; `cpu_baseline`
 times the plain FP64 CPU oracle on a bounded sample of the same workload.
+`mixed`: the 120-atom workload built in FP64 and in mixed precision (speedup,
+E2 difference).  `grad`: the 60-atom workload's forward (J/K + E2) and
+backward (nuclear gradient) times.
 """
 import argparse
 import json
@@ -100,15 +103,79 @@ def mixed_comparison(torch, mjk, inputs, dev, taus=(1e-4,), steps=2):
     return out
 
 
+def grad_comparison(torch, mjk, inputs, dev, steps=2, warmup=1):
+    """60-atom s,s,p,d workload, no screening: forward (J/K build + E2) and
+    backward (nuclear gradient at fixed D) times with HIP events on the launch
+    stream, and the per-class gradient kernel times."""
+    cfg = inputs.make_config(5)
+    b = cfg["basis"]
+    D = torch.as_tensor(cfg["D"], device=f"cuda:{dev}")
+    t0 = time.time()
+    plan = mjk.Plan(b, tau=cfg["tau"], device=dev, grad=True)
+    torch.cuda.synchronize()
+    plan_ms = (time.time() - t0) * 1e3
+    J = torch.empty_like(D)
+    K = torch.empty_like(D)
+    e = torch.empty((), dtype=torch.float64, device=f"cuda:{dev}")
+    g = torch.empty((b["xyz"].shape[0], 3), dtype=torch.float64, device=f"cuda:{dev}")
+    for _ in range(warmup):
+        plan.build_jk(D, J, K)
+        plan.e2(D, J, K, e)
+        plan.grad_e2(D, g)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd = bwd = 0.0
+    per_cls = {}
+    for _ in range(steps):
+        plan.set_timing(False)
+        ev[0].record()
+        plan.build_jk(D, J, K)
+        plan.e2(D, J, K, e)
+        ev[1].record()
+        plan.set_timing(True)
+        plan.grad_e2(D, g)
+        ev[2].record()
+        torch.cuda.synchronize()
+        fwd += ev[0].elapsed_time(ev[1])
+        bwd += ev[1].elapsed_time(ev[2])
+        for t in plan.timings():
+            acc = per_cls.setdefault(t["cls"], {"ms": 0.0, "nlaunch": 0, "flops": 0.0})
+            acc["ms"] += t["ms"]
+            acc["nlaunch"] += t["nlaunch"]
+            acc["flops"] += t["flops"]
+    fwd /= steps
+    bwd /= steps
+    print(f"bench: 60-atom gradient: forward {fwd:.1f} ms, backward {bwd:.1f} ms", file=sys.stderr, flush=True)
+    gh = g.cpu().numpy()
+    dom_cls, dom = max(per_cls.items(), key=lambda kv: kv[1]["ms"])
+    gfl = plan.stats["grad_flops_kept"]
+    return {
+        "workload": "60-atom jittered-lattice molecule, s,s,p,d x 3 primitives, nbf 660, no screening, FP64",
+        "nbf": b["nbf"], "quartets": plan.stats["nquartet_kept"], "plan_ms": plan_ms,
+        "forward_ms": fwd, "backward_ms": bwd, "backward_over_forward": bwd / fwd,
+        "e2": float(e.item()), "sum_rule_max_abs": float(np.max(np.abs(gh.sum(axis=0)))),
+        "max_abs_grad": float(np.max(np.abs(gh))),
+        "backward_algorithmic_tflops": gfl / (bwd * 1e-3) / 1e12,
+        "dominant_kernel": {"kernel": f"k_grad<{dom_cls}>", "avg_launch_ms": dom["ms"] / dom["nlaunch"],
+                            "achieved_tflops": dom["flops"] / (dom["ms"] * 1e-3) / 1e12,
+                            "frac": dom["flops"] / (dom["ms"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS},
+        "classes": {k: {"ms": round(v["ms"] / steps, 3),
+                        "tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3) if v["ms"] > 0 else None}
+                    for k, v in sorted(per_cls.items(), key=lambda kv: -kv[1]["ms"])},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mixed", action="store_true",
-                    help="also run the 120-atom mixed-precision comparison (FP32 below Q_AB Q_CD = 1e-4) "
-                         "and report its speedup over the FP64 path and its E2 difference")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the 120-atom mixed-precision comparison (FP32 below Q_AB Q_CD = fp32_tau: "
+                         "speedup over the FP64 path and E2 difference)")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the 60-atom nuclear-gradient timing (backward / forward ratio)")
     ap.add_argument("--fp32-tau", type=float, nargs="+", default=[1e-4],
                     help="mixed-precision thresholds for --mixed (first one is the headline)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -233,8 +300,10 @@ def main():
         "classes": classes,
         "parity_vs_stored_oracle_blocks": {"max_abs_dJ": dj, "max_abs_dK": dk},
     }
-    if args.mixed:
+    if not args.no_mixed:
         out["mixed"] = mixed_comparison(torch, mjk, inputs, dev, taus=args.fp32_tau)
+    if not args.no_grad:
+        out["grad"] = grad_comparison(torch, mjk, inputs, dev)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)

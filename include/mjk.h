@@ -53,6 +53,7 @@ extern "C" {
 
 /* Flags of mjk_jk_opts.flags */
 #define MJK_FLAG_CHECK 0x1u       /* check D on the host side of the call: finite and symmetric */
+#define MJK_FLAG_GRAD 0x2u        /* size the workspace for mjk_grad_e2 as well                 */
 
 typedef struct mjk_ctx mjk_ctx;
 typedef struct mjk_plan mjk_plan;
@@ -102,10 +103,18 @@ typedef struct mjk_plan_stats {
     int64_t nlaunch;            /* kernel launches per mjk_build_jk                */
     double vrr_flops_kept;      /* algorithmic flops of the kept quartets          */
     size_t workspace_bytes;
+    double grad_flops_kept;     /* algorithmic flops of mjk_grad_e2 (MJK_FLAG_GRAD) */
 } mjk_plan_stats;
 
 /* Library identification: lmax of the build (highest shell l supported). */
 int mjk_lmax(void);
+
+/* Quartet classes of the build: classes (la lb | lc ld) with la >= lb,
+ * lc >= ld and pair class (la, lb) >= (lc, ld), indexed X(X+1)/2 + Y over
+ * pair classes X = la(la+1)/2 + lb (Section 5: quartets grouped by
+ * angular momentum).  mjk_class_l writes la, lb, lc, ld of class q. */
+int mjk_num_classes(void);
+int mjk_class_l(int32_t q, int32_t *l4);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *mjk_last_error(void);
@@ -139,6 +148,30 @@ int mjk_plan_bind(mjk_plan *plan, void *workspace, size_t bytes, void *stream);
  * host and checked first (finite, symmetric to 1e-12 max|D|). */
 int mjk_build_jk(mjk_plan *plan, const double *D, double *J, double *K, void *stream);
 
+/* E2 = 1/2 Tr(DJ) - 1/4 Tr(DK), the two-electron energy of a closed-shell
+ * density D with its J and K (Section 2.1's Fock build: E2 is the energy
+ * whose derivative with respect to D is J - K/2).  D, J, K: device float64
+ * nbf x nbf; e2: one device float64, overwritten.  Asynchronous. */
+int mjk_e2(mjk_plan *plan, const double *D, const double *J, const double *K, double *e2, void *stream);
+
+/* Nuclear gradient of E2 at fixed D: grad[3*atom + i] = dE2/dR_{atom,i},
+ * device float64 natom x 3, overwritten.  The basis functions move with
+ * their atoms; d(ab|cd)/dA_i = 2 alpha (a+1_i b|cd) - a_i (a-1_i b|cd) on
+ * three centres of every kept unique quartet, the fourth by translational
+ * invariance, contracted with 4 D_ab D_cd - D_ac D_bd - D_ad D_bc.  Every
+ * kept quartet is evaluated in FP64 (fp32_tau does not apply).  The plan
+ * must have been created with MJK_FLAG_GRAD (else MJK_ERR_STATE); natom is
+ * limited to 1024 (MJK_ERR_UNSUPPORTED).  Asynchronous on `stream`; with
+ * timing enabled the per-class events cover this call's launches. */
+int mjk_grad_e2(mjk_plan *plan, const double *D, double *grad, void *stream);
+
+/* Per-class work per lane (Section 7, Algorithm 2's workload): qpl[q]
+ * quartets per lane for class q (1, 2, 4, 8 or 16; n = mjk_num_classes()),
+ * i.e. a wave takes one bra pair and 64 * qpl[q] of its kets.  Default 1.
+ * Rebuilds the plan's work lists (host, then a synchronous upload; waits for
+ * the device to be idle first).  Results change only in summation order. */
+int mjk_plan_set_tiles(mjk_plan *plan, const int32_t *qpl, int32_t n);
+
 /* Explicit contracted ERI blocks (Eq. 2) for nq shell quartets.
  * quartets: host int32, nq x 4 shell indices (A, B, C, D) in any order.
  * out: device float64; quartet q occupies na*nb*nc*nd values, row-major over
@@ -164,7 +197,9 @@ int mjk_plan_stats_get(const mjk_plan *plan, mjk_plan_stats *stats);
  * quartet: horizontal recurrence and digestion, 12 flops per integral).
  * out: host array of cap records; *n receives the number of classes with
  * work (at most cap are written).  Synchronizes nothing itself; returns
- * MJK_ERR_STATE if timing was off during the last build. */
+ * MJK_ERR_STATE if timing was off during the last build.  After
+ * mjk_grad_e2 the records describe that call (flops: its algorithmic work,
+ * all shifted classes of each class). */
 typedef struct mjk_class_timing {
     int32_t la, lb, lc, ld;
     int32_t nlaunch;
@@ -178,6 +213,52 @@ int mjk_plan_set_timing(mjk_plan *plan, int enable);
 int mjk_plan_timings(mjk_plan *plan, mjk_class_timing *out, int32_t cap, int32_t *n);
 
 void mjk_plan_destroy(mjk_plan *plan);
+
+/* ---- Batches: many molecules of uneven size in one launch per class ----
+ * Section 5's blocks of every molecule, concatenated: each launch takes the
+ * work of one quartet class (at one precision) for all molecules, costliest
+ * segments first, and persistent waves pull work items from an atomic
+ * counter.  Molecule m's D, J, K are nbf_m x nbf_m row-major blocks packed
+ * back to back in one device buffer, at the element offsets given by
+ * mjk_batch_offsets (nmol + 1 values, the last = total length).  The
+ * results equal those of separate plans up to summation order.
+ *
+ * mjk_batch_create: validates every molecule (as mjk_plan_create) with the
+ *   same options (no MJK_FLAG_GRAD); reports the workspace bytes.
+ * mjk_batch_bind: builds every molecule's tables in the workspace
+ *   (synchronizes `stream` once per molecule).
+ * mjk_batch_build_jk: J and K of every molecule, overwritten; asynchronous.
+ * mjk_batch_set_tiles: per-class quartets per lane, as mjk_plan_set_tiles.
+ * mjk_batch_autotune: Algorithm 2 on this batch: all classes start at one
+ *   quartet per lane; each sweep times a class alone (shortest of `reps`
+ *   launches), doubles its workload (Combine), times it again and keeps the
+ *   change if faster, else halves it back (Revert) and leaves the class;
+ *   sweeps repeat while any class improved.  The chosen table is written to
+ *   qpl_out (n = mjk_num_classes()) and left active.  Synchronous; J and K
+ *   hold no meaningful values afterwards.
+ * mjk_batch_set_stamps: record per-molecule wall-clock stamps (first work
+ *   item started, last work item finished) during builds;
+ *   mjk_batch_mol_times converts those of the last build to milliseconds
+ *   since the earliest start, ms[2m], ms[2m+1] (synchronous).
+ * mjk_batch_set_timing / mjk_batch_timings: per-class event timing, as for
+ *   plans.
+ * mjk_batch_stats: totals over molecules; nq_per_mol (optional, nmol values)
+ *   receives each molecule's kept quartets. */
+typedef struct mjk_batch mjk_batch;
+int mjk_batch_create(mjk_ctx *ctx, int32_t nmol, const mjk_basis *mols, const mjk_jk_opts *opts, mjk_batch **out,
+                     size_t *workspace_bytes);
+int mjk_batch_bind(mjk_batch *batch, void *workspace, size_t bytes, void *stream);
+int mjk_batch_offsets(const mjk_batch *batch, int64_t *mat_off);
+int mjk_batch_build_jk(mjk_batch *batch, const double *D, double *J, double *K, void *stream);
+int mjk_batch_set_tiles(mjk_batch *batch, const int32_t *qpl, int32_t n);
+int mjk_batch_autotune(mjk_batch *batch, const double *D, double *J, double *K, int32_t reps, int32_t *qpl_out,
+                       int32_t n, void *stream);
+int mjk_batch_set_stamps(mjk_batch *batch, int enable);
+int mjk_batch_mol_times(mjk_batch *batch, double *ms);
+int mjk_batch_set_timing(mjk_batch *batch, int enable);
+int mjk_batch_timings(mjk_batch *batch, mjk_class_timing *out, int32_t cap, int32_t *n);
+int mjk_batch_stats(const mjk_batch *batch, mjk_plan_stats *total, int64_t *nq_per_mol);
+void mjk_batch_destroy(mjk_batch *batch);
 
 #ifdef __cplusplus
 }

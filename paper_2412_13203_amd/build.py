@@ -41,8 +41,9 @@ def generate(lmax: int = 2):
     finally:
         sys.path.pop(0)
     if os.path.isdir(GEN):
-        for f in glob.glob(os.path.join(GEN, "tu_*.hip")):
-            os.remove(f)
+        for pat in ("tu_*.hip", "cls_*.inc", "eri_classes.inc"):
+            for f in glob.glob(os.path.join(GEN, pat)):
+                os.remove(f)
     boys_gen.generate(GEN)
     _, tus = eri_gen.generate(GEN, lmax)
     return tus
@@ -86,8 +87,9 @@ def build(verbose: bool = True, jobs: int | None = None, lmax: int = 2, out: str
 
 
 def _weight(tu):
-    name = os.path.basename(tu)[3:-4]
-    return sum("spdf".index(c) for c in name) * 10 + len(name)
+    name = os.path.basename(tu)[:-4].split("_")[-1]
+    w = sum("spdf".index(c) for c in name) * 10
+    return w * 4 if "tu_grad_" in tu else w
 
 
 if __name__ == "__main__":

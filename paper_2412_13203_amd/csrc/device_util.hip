@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_pair_table(const ShellPairD *__restrict
     }
     const double c0 = 0x1.7a8ed27904870p+2;  // sqrt(2) pi^(5/4) = 5.914967172795613
     o.K = c0 * sh.coefs[ia] * sh.coefs[jb] * exp(-al * be * ip * ab2) * ip;
-    o.pad = 0.0;
+    o.alpha = al;
     out[t] = o;
 }
 
@@ -79,6 +79,30 @@ __global__ __launch_bounds__(256) void k_symmetrize(double *__restrict__ M, int 
     }
 }
 
+// E2 = sum_ij D_ij (J_ij / 2 - K_ij / 4): one block, fixed summation order
+// (strided partial sums, then a tree in LDS), so repeated calls agree bitwise.
+__global__ __launch_bounds__(1024) void k_e2(const double *__restrict__ D, const double *__restrict__ J,
+                                             const double *__restrict__ K, int64_t n2, double *__restrict__ e2)
+{
+    __shared__ double part[1024];
+    double s = 0.0;
+    for (int64_t t = threadIdx.x; t < n2; t += 1024) s += D[t] * (0.5 * J[t] - 0.25 * K[t]);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 512; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *e2 = part[0];
+}
+
+int launch_e2(const double *D, const double *J, const double *K, int n, double *e2, hipStream_t s)
+{
+    if (n <= 0) return -1;
+    hipLaunchKernelGGL(k_e2, dim3(1), dim3(1024), 0, s, D, J, K, (int64_t)n * n, e2);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_pair_table(const ShellPairD *pairs, int npair, const double *xyz, const int32_t *atom,
                       const int32_t *prim_off, const int32_t *nprim, const double *exps, const double *coefs,
                       PrimPairD *out, int nprim_pair, hipStream_t s)
@@ -94,6 +118,36 @@ int launch_fill(double *x, int64_t n, double v, hipStream_t s)
 {
     if (n <= 0) return 0;
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, v);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ x, int64_t n, uint32_t v)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[t] = v;
+}
+
+// per molecule: [first start, last end] = [max, 0] before a build
+__global__ __launch_bounds__(256) void k_stamp_init(unsigned long long *__restrict__ x, int n)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) {
+        x[2 * t] = ~0ull;
+        x[2 * t + 1] = 0ull;
+    }
+}
+
+int launch_fill_u32(uint32_t *x, int64_t n, uint32_t v, hipStream_t s)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, v);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_stamp_init(unsigned long long *x, int n, hipStream_t s)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_stamp_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

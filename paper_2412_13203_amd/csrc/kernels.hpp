@@ -32,7 +32,6 @@ struct EriSplit;
 #include "gen/boys_table.inc"
 
 namespace mjk {
-#include "gen/eri_classes.inc"
 
 __host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 
@@ -114,11 +113,16 @@ __device__ __forceinline__ PrimPairD load_prim(const PrimPairD *__restrict__ p)
 }
 
 
+// Primitive weights of the derivative integrals: none, 2 alpha (first bra
+// centre), 2 beta (second bra centre), 2 gamma (first ket centre).
+enum { WK_ONE = 0, WK_A = 1, WK_B = 2, WK_C = 3 };
+
 // Loop over the primitive quartets of one shell quartet, ket primitives
 // outer (each lane loads its own ket record once), bra primitives inner
 // (wave-uniform records: scalar loads).  body(F, g) receives
-// [00|00]^(m) = prefactor * F_m(T), m = 0..L, and the recurrence geometry.
-template <int L, typename Body>
+// [00|00]^(m) = prefactor * F_m(T), m = 0..L, and the recurrence geometry;
+// WK != WK_ONE also multiplies the prefactor by that primitive weight.
+template <int L, int WK = WK_ONE, typename Body>
 __device__ __forceinline__ void prim_loop(const ShellPairD &bra, const ShellPairD &ket,
                                           const PrimPairD *__restrict__ prims, bool active, Body &&body)
 {
@@ -129,7 +133,10 @@ __device__ __forceinline__ void prim_loop(const ShellPairD &bra, const ShellPair
             const PrimPairD bp = load_prim(prims + bra.prim_off + ib);
             VrrGeom<double> g;
             double T;
-            const double pref = prim_geom(bp, kp, g, T);
+            double pref = prim_geom(bp, kp, g, T);
+            if constexpr (WK == WK_A) pref *= 2.0 * bp.alpha;
+            if constexpr (WK == WK_B) pref *= 2.0 * (bp.p - bp.alpha);
+            if constexpr (WK == WK_C) pref *= 2.0 * kp.alpha;
             double F[L + 1];
             boys_fm<L>(T, F);
 #pragma unroll
@@ -189,8 +196,65 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 // ---------------------------------------------------------------------------
+// Work items.  A launch covers the segments of one class (bin pairs of one or
+// many molecules); item i belongs to the last segment with item_begin <= i,
+// and inside it to the bra whose chunk range holds it.  All of this is
+// wave-uniform (scalar loads).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_seg(const JKLaunch &a, int item)
+{
+    int lo = 0, hi = a.nseg;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.segs[mid].item_begin <= item)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void locate(const JKSeg &sg, int local, int &b, int &kbeg, int &kend)
+{
+    int lo = 0, hi = sg.nbra;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sg.chunk_prefix[mid] <= local)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    b = lo;
+    kbeg = sg.ket_start[b] + (local - sg.chunk_prefix[b]) * sg.chunk;
+    kend = min(kbeg + sg.chunk, sg.ket_end[b]);
+}
+
+// persistent blocks (one wave each) take items from the launch's counter;
+// the item is wave-uniform and is kept in a scalar register, so that the
+// segment and pair records decoded from it are scalar loads, as they are for
+// a block-indexed item
+__device__ __forceinline__ int next_item(const JKLaunch &a, int lane)
+{
+    int v = 0;
+    if (lane == 0) v = (int)atomicAdd(a.queue, 1u);
+    return __builtin_amdgcn_readfirstlane(__shfl(v, 0, 64));
+}
+
+// per-molecule wall-clock stamps: first item start, last item end
+__device__ __forceinline__ void stamp(const JKLaunch &a, int mol, int lane, bool end)
+{
+    if (a.stamps != nullptr && lane == 0) {
+        const unsigned long long t = (unsigned long long)wall_clock64();
+        if (end)
+            atomicMax(a.stamps + 2 * mol + 1, t);
+        else
+            atomicMin(a.stamps + 2 * mol, t);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Fused J/K: one wave = one bra pair (uniform) x up to 64 ket pairs per
-// round (one per lane).  Digestion of (ab|cd) with the 8-fold symmetry of a
+// round (one per lane), `chunk` kets per item.  Digestion of (ab|cd) with the 8-fold symmetry of a
 // unique quartet, weight w = 1/(s_AB s_CD s_ABCD):
 //   Jt_ab += 2w D_cd   Jt_cd += 2w D_ab
 //   Kt_ac += w D_bd    Kt_ad += w D_bc    Kt_bc += w D_ad    Kt_bd += w D_ac
@@ -204,22 +268,16 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     const int item = blockIdx.x;
     const int lane = threadIdx.x;
-    // bra of this item: chunk_prefix[b] <= item < chunk_prefix[b + 1]
-    int lo = 0, hi = a.nbra;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (a.chunk_prefix[mid] <= item)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    const int b = lo;
-    const int kbeg = a.ket_start[b] + (item - a.chunk_prefix[b]) * a.chunk;
-    const int kend = min(kbeg + a.chunk, a.ket_end[b]);
-    const int bra_pos = a.bra_begin + b;
-    const ShellPairD bra = a.pairs[bra_pos];
-    const int N = a.nbf;
-    const double *__restrict__ D = a.D;
+    const JKSeg sg = a.segs[find_seg(a, item)];
+    int b, kbeg, kend;
+    locate(sg, item - sg.item_begin, b, kbeg, kend);
+    stamp(a, sg.mol, lane, false);
+    const int bra_pos = sg.bra_begin + b;
+    const ShellPairD bra = sg.pairs[bra_pos];
+    const int N = sg.nbf;
+    const double *__restrict__ D = a.D + sg.mat_off;
+    double *__restrict__ Jm = a.J + sg.mat_off;
+    double *__restrict__ Km = a.K + sg.mat_off;
 
     double Dab[NA * NB];
 #pragma unroll
@@ -233,10 +291,10 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
     for (int k0 = kbeg; k0 < kend; k0 += 64) {
         const int k = k0 + lane;
         const bool active = k < kend;
-        const int ket_pos = a.ket_begin + (active ? k : kbeg);
-        const ShellPairD ket = a.pairs[ket_pos];
+        const int ket_pos = sg.ket_begin + (active ? k : kbeg);
+        const ShellPairD ket = sg.pairs[ket_pos];
         T acc[C::NACC];
-        contract_quartet<LA, LB, LC, LD, T>(bra, ket, a.prims, active, acc);
+        contract_quartet<LA, LB, LC, LD, T>(bra, ket, sg.prims, active, acc);
         double eri[C::NOUT];
         if constexpr (sizeof(T) == sizeof(double)) {
             C::template hrr<double>(acc, bra.AB, ket.AB, eri);
@@ -252,7 +310,7 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
         double s = 1.0;
         if (bra.same) s *= 2.0;
         if (ket.same) s *= 2.0;
-        if (a.same_bin && ket_pos == bra_pos) s *= 2.0;
+        if (sg.same_bin && ket_pos == bra_pos) s *= 2.0;
         const double w = active ? 1.0 / s : 0.0;
 
         double Dcd[NC * ND];
@@ -275,7 +333,7 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
 #pragma unroll
                 for (int ab = 0; ab < NA * NB; ++ab) t += eri[ab * NC * ND + cd] * Dab[ab];
                 const int c = cd / ND, d = cd % ND;
-                atomicAdd(a.J + (size_t)(ket.ao_a + c) * N + ket.ao_b + d, 2.0 * w * t);
+                atomicAdd(Jm + (size_t)(ket.ao_a + c) * N + ket.ao_b + d, 2.0 * w * t);
             }
             // Kt_ac += w sum_{b,d} (ab|cd) D_bd ; Kt_ad += w sum_{b,c} (ab|cd) D_bc
 #pragma unroll
@@ -289,7 +347,7 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
                         for (int d = 0; d < ND; ++d)
                             t += eri[((ia * NB + jb) * NC + c) * ND + d] *
                                  D[(size_t)(bra.ao_b + jb) * N + ket.ao_b + d];
-                    atomicAdd(a.K + (size_t)(bra.ao_a + ia) * N + ket.ao_a + c, w * t);
+                    atomicAdd(Km + (size_t)(bra.ao_a + ia) * N + ket.ao_a + c, w * t);
                 }
 #pragma unroll
                 for (int d = 0; d < ND; ++d) {
@@ -300,7 +358,7 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
                         for (int c = 0; c < NC; ++c)
                             t += eri[((ia * NB + jb) * NC + c) * ND + d] *
                                  D[(size_t)(bra.ao_b + jb) * N + ket.ao_a + c];
-                    atomicAdd(a.K + (size_t)(bra.ao_a + ia) * N + ket.ao_b + d, w * t);
+                    atomicAdd(Km + (size_t)(bra.ao_a + ia) * N + ket.ao_b + d, w * t);
                 }
             }
             // Kt_bc += w sum_{a,d} (ab|cd) D_ad ; Kt_bd += w sum_{a,c} (ab|cd) D_ac
@@ -315,7 +373,7 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
                         for (int d = 0; d < ND; ++d)
                             t += eri[((ia * NB + jb) * NC + c) * ND + d] *
                                  D[(size_t)(bra.ao_a + ia) * N + ket.ao_b + d];
-                    atomicAdd(a.K + (size_t)(bra.ao_b + jb) * N + ket.ao_a + c, w * t);
+                    atomicAdd(Km + (size_t)(bra.ao_b + jb) * N + ket.ao_a + c, w * t);
                 }
 #pragma unroll
                 for (int d = 0; d < ND; ++d) {
@@ -326,7 +384,7 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
                         for (int c = 0; c < NC; ++c)
                             t += eri[((ia * NB + jb) * NC + c) * ND + d] *
                                  D[(size_t)(bra.ao_a + ia) * N + ket.ao_a + c];
-                    atomicAdd(a.K + (size_t)(bra.ao_b + jb) * N + ket.ao_b + d, w * t);
+                    atomicAdd(Km + (size_t)(bra.ao_b + jb) * N + ket.ao_b + d, w * t);
                 }
             }
         }
@@ -334,8 +392,9 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
 #pragma unroll
     for (int ab = 0; ab < NA * NB; ++ab) {
         const double t = wave_sum(jab[ab]);
-        if (lane == 0) atomicAdd(a.J + (size_t)(bra.ao_a + ab / NB) * N + bra.ao_b + ab % NB, t);
+        if (lane == 0) atomicAdd(Jm + (size_t)(bra.ao_a + ab / NB) * N + bra.ao_b + ab % NB, t);
     }
+    stamp(a, sg.mol, lane, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -414,7 +473,7 @@ __global__ __launch_bounds__(64) void k_schwarz(SchwarzLaunch a)
 //            lane, with the bra-uniform Jt_ab kept per lane across the item.
 // Blocks are persistent (grid = staging slots) and stride over the items.
 // ---------------------------------------------------------------------------
-template <int LA, int LB, int LC, int LD, int P, typename T>
+template <int LA, int LB, int LC, int LD, int P, typename T, int WK = WK_ONE>
 __device__ __forceinline__ void split_pass(const ShellPairD &bra, const ShellPairD &ket,
                                            const PrimPairD *__restrict__ prims, bool active,
                                            double *__restrict__ stage, int lane)
@@ -425,7 +484,7 @@ __device__ __forceinline__ void split_pass(const ShellPairD &bra, const ShellPai
     T acc[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) acc[i] = T(0);
-    prim_loop<L>(bra, ket, prims, active, [&](const double *F, const VrrGeom<double> &g) {
+    prim_loop<L, WK>(bra, ket, prims, active, [&](const double *F, const VrrGeom<double> &g) {
         if constexpr (sizeof(T) == sizeof(double)) {
             S::template vrr<P, double>(F, g, acc);
         } else {
@@ -447,14 +506,14 @@ __device__ __forceinline__ void split_pass(const ShellPairD &bra, const ShellPai
     for (int j = 0; j < NP; ++j) sl[S::template gmap<P>(j) * 64] = (double)acc[j];
 }
 
-template <int LA, int LB, int LC, int LD, int P, typename T>
+template <int LA, int LB, int LC, int LD, int P, typename T, int WK = WK_ONE>
 __device__ __forceinline__ void split_passes(const ShellPairD &bra, const ShellPairD &ket,
                                              const PrimPairD *__restrict__ prims, bool active,
                                              double *__restrict__ stage, int lane)
 {
     if constexpr (P < EriSplit<LA, LB, LC, LD>::NPASS) {
-        split_pass<LA, LB, LC, LD, P, T>(bra, ket, prims, active, stage, lane);
-        split_passes<LA, LB, LC, LD, P + 1, T>(bra, ket, prims, active, stage, lane);
+        split_pass<LA, LB, LC, LD, P, T, WK>(bra, ket, prims, active, stage, lane);
+        split_passes<LA, LB, LC, LD, P + 1, T, WK>(bra, ket, prims, active, stage, lane);
     }
 }
 
@@ -474,144 +533,162 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
     __shared__ double s_w[64];
     __shared__ int s_ao[64][2];
     const int lane = threadIdx.x;
-    const int N = a.nbf;
-    const double *__restrict__ D = a.D;
     double *stage = a.stage + (size_t)blockIdx.x * NACC * 64;
 
-    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
-        int lo = 0, hi = a.nbra;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (a.chunk_prefix[mid] <= item)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        const int b = lo;
-        const int kbeg = a.ket_start[b] + (item - a.chunk_prefix[b]) * a.chunk;
-        const int kend = min(kbeg + a.chunk, a.ket_end[b]);
-        const int nact = min(kend - kbeg, 64);
-        const int bra_pos = a.bra_begin + b;
-        const ShellPairD bra = a.pairs[bra_pos];
-
-        // phase 1: one quartet per lane, passes into the staging slot
-        const int k = kbeg + lane;
-        const bool active = lane < nact;
-        const int ket_pos = a.ket_begin + (active ? k : kbeg);
-        const ShellPairD ket = a.pairs[ket_pos];
-        split_passes<LA, LB, LC, LD, 0, T>(bra, ket, a.prims, active, stage, lane);
-        {
-            double s = 1.0;
-            if (bra.same) s *= 2.0;
-            if (ket.same) s *= 2.0;
-            if (a.same_bin && ket_pos == bra_pos) s *= 2.0;
-            s_w[lane] = active ? 1.0 / s : 0.0;
-            s_CD[lane][0] = ket.AB[0];
-            s_CD[lane][1] = ket.AB[1];
-            s_CD[lane][2] = ket.AB[2];
-            s_ao[lane][0] = ket.ao_a;
-            s_ao[lane][1] = ket.ao_b;
-        }
+    for (;;) {
+        const int item = next_item(a, lane);
+        if (item >= a.nitems) break;
+        const JKSeg sg = a.segs[find_seg(a, item)];
+        int b, kbeg, kend;
+        locate(sg, item - sg.item_begin, b, kbeg, kend);
+        stamp(a, sg.mol, lane, false);
+        const int bra_pos = sg.bra_begin + b;
+        const ShellPairD bra = sg.pairs[bra_pos];
+        const int N = sg.nbf;
+        const double *__restrict__ D = a.D + sg.mat_off;
+        double *__restrict__ Jm = a.J + sg.mat_off;
+        double *__restrict__ Km = a.K + sg.mat_off;
         for (int t = lane; t < NAB; t += 64) s_Dab[t] = D[(size_t)(bra.ao_a + t / NB) * N + bra.ao_b + t % NB];
-        __syncthreads();
-
-        // phase 2: the wave works through the item's quartets
         double jab = 0.0;  // Jt_ab for ab = lane (lane < NAB), summed over the item
-        for (int q = 0; q < nact; ++q) {
-            for (int t = lane; t < NACC; t += 64) s_buf[t] = stage[(size_t)t * 64 + q];
-            const int ao_c = s_ao[q][0], ao_d = s_ao[q][1];
-            for (int t = lane; t < NCD; t += 64) s_Dcd[t] = D[(size_t)(ao_c + t / ND) * N + ao_d + t % ND];
-            for (int t = lane; t < NA * NC; t += 64) s_Dac[t] = D[(size_t)(bra.ao_a + t / NC) * N + ao_c + t % NC];
-            for (int t = lane; t < NA * ND; t += 64) s_Dad[t] = D[(size_t)(bra.ao_a + t / ND) * N + ao_d + t % ND];
-            for (int t = lane; t < NB * NC; t += 64) s_Dbc[t] = D[(size_t)(bra.ao_b + t / NC) * N + ao_c + t % NC];
-            for (int t = lane; t < NB * ND; t += 64) s_Dbd[t] = D[(size_t)(bra.ao_b + t / ND) * N + ao_d + t % ND];
+
+        for (int k0 = kbeg; k0 < kend; k0 += 64) {
+            // phase 1: one quartet per lane, passes into the staging slot
+            const int nact = min(kend - k0, 64);
+            const bool active = lane < nact;
+            const int ket_pos = sg.ket_begin + (active ? k0 + lane : k0);
+            const ShellPairD ket = sg.pairs[ket_pos];
+            split_passes<LA, LB, LC, LD, 0, T>(bra, ket, sg.prims, active, stage, lane);
+            {
+                double s = 1.0;
+                if (bra.same) s *= 2.0;
+                if (ket.same) s *= 2.0;
+                if (sg.same_bin && ket_pos == bra_pos) s *= 2.0;
+                s_w[lane] = active ? 1.0 / s : 0.0;
+                s_CD[lane][0] = ket.AB[0];
+                s_CD[lane][1] = ket.AB[1];
+                s_CD[lane][2] = ket.AB[2];
+                s_ao[lane][0] = ket.ao_a;
+                s_ao[lane][1] = ket.ao_b;
+            }
             __syncthreads();
-            for (int f = lane; f < NF; f += 64) S::template hrr_bra_col<double>(s_buf, f, bra.AB, s_abf);
-            __syncthreads();
-            const double CD[3] = {s_CD[q][0], s_CD[q][1], s_CD[q][2]};
-            const double w = s_w[q];
-            for (int r = lane; r < NAB; r += 64) {
-                double row[NCD];
-                S::template hrr_ket_row<double>(s_abf + r * NF, CD, row);
-                double t = 0.0;
+
+            // phase 2: the wave works through this round's quartets
+            for (int q = 0; q < nact; ++q) {
+                for (int t = lane; t < NACC; t += 64) s_buf[t] = stage[(size_t)t * 64 + q];
+                const int ao_c = s_ao[q][0], ao_d = s_ao[q][1];
+                for (int t = lane; t < NCD; t += 64) s_Dcd[t] = D[(size_t)(ao_c + t / ND) * N + ao_d + t % ND];
+                for (int t = lane; t < NA * NC; t += 64)
+                    s_Dac[t] = D[(size_t)(bra.ao_a + t / NC) * N + ao_c + t % NC];
+                for (int t = lane; t < NA * ND; t += 64)
+                    s_Dad[t] = D[(size_t)(bra.ao_a + t / ND) * N + ao_d + t % ND];
+                for (int t = lane; t < NB * NC; t += 64)
+                    s_Dbc[t] = D[(size_t)(bra.ao_b + t / NC) * N + ao_c + t % NC];
+                for (int t = lane; t < NB * ND; t += 64)
+                    s_Dbd[t] = D[(size_t)(bra.ao_b + t / ND) * N + ao_d + t % ND];
+                __syncthreads();
+                for (int f = lane; f < NF; f += 64) S::template hrr_bra_col<1, double>(s_buf, f, bra.AB, s_abf);
+                __syncthreads();
+                const double CD[3] = {s_CD[q][0], s_CD[q][1], s_CD[q][2]};
+                const double w = s_w[q];
+                for (int r = lane; r < NAB; r += 64) {
+                    double row[NCD];
+                    S::template hrr_ket_row<double>(s_abf + r * NF, CD, row);
+                    double t = 0.0;
 #pragma unroll
-                for (int cd = 0; cd < NCD; ++cd) {
-                    s_buf[r * NCD + cd] = row[cd];
-                    t += row[cd] * s_Dcd[cd];
+                    for (int cd = 0; cd < NCD; ++cd) {
+                        s_buf[r * NCD + cd] = row[cd];
+                        t += row[cd] * s_Dcd[cd];
+                    }
+                    jab += 2.0 * w * t;
                 }
-                jab += 2.0 * w * t;
+                __syncthreads();
+                // Jt_cd += 2w sum_ab (ab|cd) D_ab
+                for (int t = lane; t < NCD; t += 64) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int ab = 0; ab < NAB; ++ab) v += s_buf[ab * NCD + t] * s_Dab[ab];
+                    atomicAdd(Jm + (size_t)(ao_c + t / ND) * N + ao_d + t % ND, 2.0 * w * v);
+                }
+                // Kt_ac += w sum_{b,d} (ab|cd) D_bd
+                for (int t = lane; t < NA * NC; t += 64) {
+                    const int ia = t / NC, c = t % NC;
+                    double v = 0.0;
+#pragma unroll
+                    for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+                        for (int d = 0; d < ND; ++d)
+                            v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dbd[jb * ND + d];
+                    atomicAdd(Km + (size_t)(bra.ao_a + ia) * N + ao_c + c, w * v);
+                }
+                // Kt_ad += w sum_{b,c} (ab|cd) D_bc
+                for (int t = lane; t < NA * ND; t += 64) {
+                    const int ia = t / ND, d = t % ND;
+                    double v = 0.0;
+#pragma unroll
+                    for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dbc[jb * NC + c];
+                    atomicAdd(Km + (size_t)(bra.ao_a + ia) * N + ao_d + d, w * v);
+                }
+                // Kt_bc += w sum_{a,d} (ab|cd) D_ad
+                for (int t = lane; t < NB * NC; t += 64) {
+                    const int jb = t / NC, c = t % NC;
+                    double v = 0.0;
+#pragma unroll
+                    for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                        for (int d = 0; d < ND; ++d)
+                            v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dad[ia * ND + d];
+                    atomicAdd(Km + (size_t)(bra.ao_b + jb) * N + ao_c + c, w * v);
+                }
+                // Kt_bd += w sum_{a,c} (ab|cd) D_ac
+                for (int t = lane; t < NB * ND; t += 64) {
+                    const int jb = t / ND, d = t % ND;
+                    double v = 0.0;
+#pragma unroll
+                    for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dac[ia * NC + c];
+                    atomicAdd(Km + (size_t)(bra.ao_b + jb) * N + ao_d + d, w * v);
+                }
+                __syncthreads();
             }
-            __syncthreads();
-            // Jt_cd += 2w sum_ab (ab|cd) D_ab
-            for (int t = lane; t < NCD; t += 64) {
-                double v = 0.0;
-#pragma unroll
-                for (int ab = 0; ab < NAB; ++ab) v += s_buf[ab * NCD + t] * s_Dab[ab];
-                atomicAdd(a.J + (size_t)(ao_c + t / ND) * N + ao_d + t % ND, 2.0 * w * v);
-            }
-            // Kt_ac += w sum_{b,d} (ab|cd) D_bd
-            for (int t = lane; t < NA * NC; t += 64) {
-                const int ia = t / NC, c = t % NC;
-                double v = 0.0;
-#pragma unroll
-                for (int jb = 0; jb < NB; ++jb)
-#pragma unroll
-                    for (int d = 0; d < ND; ++d) v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dbd[jb * ND + d];
-                atomicAdd(a.K + (size_t)(bra.ao_a + ia) * N + ao_c + c, w * v);
-            }
-            // Kt_ad += w sum_{b,c} (ab|cd) D_bc
-            for (int t = lane; t < NA * ND; t += 64) {
-                const int ia = t / ND, d = t % ND;
-                double v = 0.0;
-#pragma unroll
-                for (int jb = 0; jb < NB; ++jb)
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dbc[jb * NC + c];
-                atomicAdd(a.K + (size_t)(bra.ao_a + ia) * N + ao_d + d, w * v);
-            }
-            // Kt_bc += w sum_{a,d} (ab|cd) D_ad
-            for (int t = lane; t < NB * NC; t += 64) {
-                const int jb = t / NC, c = t % NC;
-                double v = 0.0;
-#pragma unroll
-                for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-                    for (int d = 0; d < ND; ++d) v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dad[ia * ND + d];
-                atomicAdd(a.K + (size_t)(bra.ao_b + jb) * N + ao_c + c, w * v);
-            }
-            // Kt_bd += w sum_{a,c} (ab|cd) D_ac
-            for (int t = lane; t < NB * ND; t += 64) {
-                const int jb = t / ND, d = t % ND;
-                double v = 0.0;
-#pragma unroll
-                for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dac[ia * NC + c];
-                atomicAdd(a.K + (size_t)(bra.ao_b + jb) * N + ao_d + d, w * v);
-            }
-            __syncthreads();
         }
-        if (lane < NAB) atomicAdd(a.J + (size_t)(bra.ao_a + lane / NB) * N + bra.ao_b + lane % NB, jab);
+        if (lane < NAB) atomicAdd(Jm + (size_t)(bra.ao_a + lane / NB) * N + bra.ao_b + lane % NB, jab);
+        stamp(a, sg.mol, lane, true);
         __syncthreads();
     }
+}
+
+// Persistent grid for kernels that pop items from the launch's counter:
+// resident blocks per CU (occupancy) x CUs, at most one block per staging
+// slot and per item.
+template <typename K>
+int persistent_grid(K kernel, size_t lds, int nitems, int nslot, bool staged)
+{
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int grid = per_cu * ncu;
+    if (staged && grid > nslot) grid = nslot;
+    if (grid > nitems) grid = nitems;
+    return grid;
 }
 
 template <int LA, int LB, int LC, int LD, typename T>
 int launch_split(const JKLaunch &a, hipStream_t s)
 {
     if (a.nitems <= 0) return 0;
-    static int per_cu = -1;
-    static int ncu = 0;
-    if (per_cu < 0) {
-        int dev = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_jk_split<LA, LB, LC, LD, T>, 64, 0) !=
-                hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
+    static int grid_cache = 0;  // occupancy bound, computed once
+    if (grid_cache == 0) {
+        grid_cache = persistent_grid(k_jk_split<LA, LB, LC, LD, T>, 0, 1 << 30, 1 << 30, false);
+        if (grid_cache <= 0) return -1;
     }
-    int grid = per_cu * ncu;
+    int grid = grid_cache;
     if (grid > a.nslot) grid = a.nslot;
     if (grid > a.nitems) grid = a.nitems;
     if (grid < 1) return -1;

@@ -9,8 +9,11 @@
 //            count (bins), and by Q descending inside a bin;
 //   stage 2: a bin pair (X, Y) forms the quartet blocks of one class; for each
 //            bra pair of X the kept kets of Y are a prefix of Y (Q-sorted,
-//            Q_AB Q_CD >= tau), cut into chunks of 64 kets, one wave each.
+//            Q_AB Q_CD >= tau), cut into chunks of 64 q kets (q quartets per
+//            lane, per class: the tile table of Algorithm 2), one wave each.
 // Quartets themselves are never stored: only per-bra prefix lengths.
+// Launches: one per (quartet class, precision); its segments are the bin
+// pairs of that class, of one molecule (plan) or of many (batch).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,6 +34,9 @@ int launch_pair_table(const ShellPairD *pairs, int npair, const double *xyz, con
                       PrimPairD *out, int nprim_pair, hipStream_t s);
 int launch_fill(double *x, int64_t n, double v, hipStream_t s);
 int launch_symmetrize(double *M, int n, hipStream_t s);
+int launch_e2(const double *D, const double *J, const double *K, int n, double *e2, hipStream_t s);
+int launch_fill_u32(uint32_t *x, int64_t n, uint32_t v, hipStream_t s);
+int launch_stamp_init(unsigned long long *x, int n, hipStream_t s);
 }  // namespace mjk
 
 using namespace mjk;
@@ -71,9 +77,11 @@ inline int kbucket(int np)
     return 5;
 }
 constexpr int kNumKBuckets = 6;
-constexpr int kChunk = 64;          // kets per work item (one per lane)
+constexpr int kChunk = 64;          // kets per work item and quartet per lane
+constexpr int kMaxQpl = 16;         // largest quartets-per-lane setting
 constexpr int kEriStage = 65536;    // eri_class items per upload
 constexpr int kSlotsPerCU = 8;      // resident waves per CU the staging is sized for
+constexpr int kGradMaxAtoms = 1024; // gradient: per-block copy of the gradient in LDS
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -87,16 +95,19 @@ struct BinPair {
     int qcls;          // quartet class index
 };
 
-// One launch: the FP64 or the FP32 part of one bin pair's quartets.
+// One segment: the FP64 or the FP32 part of one bin pair's quartets.
 struct WorkList {
     int bp;            // bin pair
     int fp32;          // 1: FP32 recurrence (Q_AB Q_CD < fp32_tau)
     size_t off;        // int offset in the work-list region:
                        //   ket_start[nbra], ket_end[nbra], chunk_prefix[nbra + 1]
+    int nbra;
+    int chunk;         // kets per item
     int nitems;
     int64_t nq;        // kept quartets
     int64_t npq;       // kept primitive quartets
     double cost;       // algorithmic flops
+    double gcost;      // algorithmic flops of the gradient
 };
 
 // flops per primitive quartet outside the vertical recurrence: geometry (26),
@@ -110,6 +121,20 @@ struct mjk_ctx {
     std::string arch;
     int ncu;
 };
+
+namespace {
+
+// One launch: the segments of one quartet class at one precision.
+struct Group {
+    int qcls = 0, fp32 = 0;
+    std::vector<std::pair<int, int>> segs;  // (molecule, work list), costliest per item first
+    size_t seg_begin = 0;                   // first JKSeg of this launch in the segment array
+    int nitems = 0;
+    int64_t nq = 0, npq = 0;
+    double cost = 0.0, gcost = 0.0;
+};
+
+}  // namespace
 
 struct mjk_plan {
     mjk_ctx *ctx;
@@ -127,29 +152,274 @@ struct mjk_plan {
     std::vector<int32_t> sorted;         // sorted position -> natural index
     std::vector<Bin> bins;
     std::vector<BinPair> bps;
-    std::vector<WorkList> lists;
+    std::vector<WorkList> lists;         // bin pair x precision, natural order
+    std::vector<int32_t> work;           // host copy of the work-list region
     std::vector<std::vector<int32_t>> class_pairs;  // natural indices per pair class
+    int qpl[kNumQuartetClasses];         // quartets per lane, per class
+    std::vector<Group> groups;
     // workspace layout (byte offsets)
-    size_t o_xyz, o_atom, o_poff, o_np, o_exps, o_coefs, o_pnat, o_psort, o_prims, o_Q, o_cls, o_work, o_eri,
-        o_stage, total;
+    size_t o_xyz, o_atom, o_poff, o_np, o_exps, o_coefs, o_pnat, o_psort, o_prims, o_Q, o_cls, o_work, o_segs,
+        o_queue, o_eri, o_stage, total;
     int nslot = 0;            // staging slots for split classes
-    size_t stage_nacc = 0;    // largest split-class accumulator count present
+    size_t stage_nacc = 0;    // largest split-class accumulator count present (J/K and gradient)
+    int64_t max_items = 0;    // upper bound of the items of one segment (one quartet per lane)
     size_t work_ints = 0;
+    bool in_batch = false;    // staging and launches belong to a batch
     char *ws = nullptr;
     bool bound = false;
     mjk_plan_stats stats{};
     // optional per-launch timing
-    bool timing = false, timed_last = false;
-    std::vector<hipEvent_t> ev;  // 2 per bin pair
+    bool timing = false, timed_last = false, timed_grad = false;
+    std::vector<hipEvent_t> ev;  // 2 per launch
     ~mjk_plan()
     {
         for (auto e : ev) hipEventDestroy(e);
     }
 };
 
+struct mjk_batch {
+    mjk_ctx *ctx;
+    std::vector<mjk_plan *> plans;
+    std::vector<size_t> ws_off;      // each molecule's plan workspace inside the batch workspace
+    std::vector<int64_t> mat_off;    // nmol + 1: packed D, J, K element offsets
+    size_t o_segs = 0, o_queue = 0, o_stamps = 0, o_stage = 0, total = 0;
+    size_t nseg = 0;
+    int nslot = 0;
+    size_t stage_nacc = 0;
+    int qpl[kNumQuartetClasses];
+    std::vector<Group> groups;
+    char *ws = nullptr;
+    bool bound = false;
+    bool stamps = false, stamped_last = false;
+    bool timing = false, timed_last = false;
+    std::vector<hipEvent_t> ev;
+    ~mjk_batch()
+    {
+        for (auto e : ev) hipEventDestroy(e);
+        for (auto *p : plans) delete p;
+    }
+};
+
+namespace {
+
+// chunk prefix and item count of every work list of class `qcls` (-1: all)
+// for the plan's quartets-per-lane table
+void rechunk(mjk_plan *p, int qcls)
+{
+    for (auto &wl : p->lists) {
+        const int qc = p->bps[wl.bp].qcls;
+        if (qcls >= 0 && qc != qcls) continue;
+        wl.chunk = kChunk * p->qpl[qc];
+        const int32_t *st = p->work.data() + wl.off, *en = st + wl.nbra;
+        int32_t *pre = p->work.data() + wl.off + 2 * (size_t)wl.nbra;
+        pre[0] = 0;
+        for (int b = 0; b < wl.nbra; ++b) pre[b + 1] = pre[b] + (en[b] - st[b] + wl.chunk - 1) / wl.chunk;
+        wl.nitems = pre[wl.nbra];
+    }
+}
+
+JKSeg make_seg(const mjk_plan *p, const WorkList &wl, int64_t mat_off, int mol)
+{
+    const BinPair &bp = p->bps[wl.bp];
+    const Bin &X = p->bins[bp.X], &Y = p->bins[bp.Y];
+    const char *w = p->ws;
+    const int32_t *wk = (const int32_t *)(w + p->o_work) + wl.off;
+    JKSeg g{};
+    g.pairs = (const ShellPairD *)(w + p->o_psort);
+    g.prims = (const PrimPairD *)(w + p->o_prims);
+    g.ket_start = wk;
+    g.ket_end = wk + X.count;
+    g.chunk_prefix = wk + 2 * X.count;
+    g.shell_atom = (const int32_t *)(w + p->o_atom);
+    g.mat_off = mat_off;
+    g.nbf = p->nbf;
+    g.bra_begin = X.begin;
+    g.nbra = X.count;
+    g.ket_begin = Y.begin;
+    g.same_bin = bp.X == bp.Y;
+    g.chunk = wl.chunk;
+    g.item_begin = 0;
+    g.mol = mol;
+    g.grad_off = 0;
+    g.natom = p->natom;
+    return g;
+}
+
+// Launch groups over the molecules' work lists: one per (class, precision),
+// segments costliest per item first (longest-first inside the launch),
+// launches costliest first.
+std::vector<Group> make_groups(const std::vector<mjk_plan *> &plans)
+{
+    std::vector<Group> gs(2 * kNumQuartetClasses);
+    for (int q = 0; q < kNumQuartetClasses; ++q)
+        for (int f = 0; f < 2; ++f) {
+            gs[2 * q + f].qcls = q;
+            gs[2 * q + f].fp32 = f;
+        }
+    for (int m = 0; m < (int)plans.size(); ++m) {
+        const mjk_plan *p = plans[m];
+        for (int li = 0; li < (int)p->lists.size(); ++li) {
+            const WorkList &wl = p->lists[li];
+            if (wl.nitems <= 0) continue;
+            Group &g = gs[2 * p->bps[wl.bp].qcls + wl.fp32];
+            g.segs.push_back({m, li});
+            g.nitems += wl.nitems;
+            g.nq += wl.nq;
+            g.npq += wl.npq;
+            g.cost += wl.cost;
+            g.gcost += wl.gcost;
+        }
+    }
+    std::vector<Group> out;
+    for (auto &g : gs) {
+        if (g.nitems == 0) continue;
+        std::stable_sort(g.segs.begin(), g.segs.end(), [&](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+            const WorkList &a = plans[x.first]->lists[x.second], &b = plans[y.first]->lists[y.second];
+            return a.cost / a.nitems > b.cost / b.nitems;
+        });
+        out.push_back(std::move(g));
+    }
+    std::stable_sort(out.begin(), out.end(), [](const Group &a, const Group &b) { return a.cost > b.cost; });
+    size_t off = 0;
+    for (auto &g : out) {
+        g.seg_begin = off;
+        off += g.segs.size();
+    }
+    return out;
+}
+
+// segment records of every group, uploaded to dsegs (synchronous on s)
+int upload_groups(const std::vector<Group> &gs, const std::vector<mjk_plan *> &plans, const int64_t *mat_off,
+                  JKSeg *dsegs, hipStream_t s)
+{
+    std::vector<JKSeg> h;
+    for (const auto &g : gs) {
+        int item = 0;
+        for (const auto &sm : g.segs) {
+            const mjk_plan *p = plans[sm.first];
+            JKSeg seg = make_seg(p, p->lists[sm.second], mat_off[sm.first], sm.first);
+            seg.item_begin = item;
+            item += p->lists[sm.second].nitems;
+            h.push_back(seg);
+        }
+    }
+    if (h.empty()) return MJK_OK;
+    HIP_TRY(hipMemcpyAsync(dsegs, h.data(), sizeof(JKSeg) * h.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));  // h is released on return
+    return MJK_OK;
+}
+
+int upload_work(mjk_plan *p, hipStream_t s)
+{
+    if (p->work.empty()) return MJK_OK;
+    HIP_TRY(hipMemcpyAsync(p->ws + p->o_work, p->work.data(), sizeof(int32_t) * p->work.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MJK_OK;
+}
+
+int ensure_events(std::vector<hipEvent_t> &ev, size_t n)
+{
+    if (ev.size() == n) return MJK_OK;
+    for (auto e : ev) hipEventDestroy(e);
+    ev.assign(n, nullptr);
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    return MJK_OK;
+}
+
+// Run every group: J/K (grad == nullptr) or the gradient.  The caller has
+// cleared the outputs; the work counters are cleared here.
+int run_groups(const std::vector<Group> &gs, const JKSeg *dsegs, uint32_t *dqueue, double *stage, int nslot,
+               const double *D, double *J, double *K, double *grad, int natom_max, unsigned long long *stamps,
+               hipStream_t s, std::vector<hipEvent_t> *ev, const char *who)
+{
+    if (gs.empty()) return MJK_OK;
+    if (launch_fill_u32(dqueue, (int64_t)gs.size(), 0u, s)) return fail(MJK_ERR_HIP, "%s: fill launch failed", who);
+    for (size_t i = 0; i < gs.size(); ++i) {
+        const Group &g = gs[i];
+        JKLaunch a{};
+        a.segs = dsegs + g.seg_begin;
+        a.nseg = (int32_t)g.segs.size();
+        a.nitems = g.nitems;
+        a.D = D;
+        a.J = J;
+        a.K = K;
+        a.grad = grad;
+        a.stage = stage;
+        a.nslot = nslot;
+        a.natom_max = natom_max;
+        a.queue = dqueue + i;
+        a.stamps = stamps;
+        const ClassEntry &ce = kClassTable[g.qcls];
+        if (ev) HIP_TRY(hipEventRecord((*ev)[2 * i], s));
+        const int rc = grad ? ce.grad(a, s) : (g.fp32 ? ce.jk32(a, s) : ce.jk(a, s));
+        if (rc) return fail(MJK_ERR_HIP, "%s: class launch failed", who);
+        if (ev) HIP_TRY(hipEventRecord((*ev)[2 * i + 1], s));
+    }
+    return MJK_OK;
+}
+
+int fill_timings(const std::vector<Group> &gs, std::vector<hipEvent_t> &ev, bool grad, mjk_class_timing *out,
+                 int32_t cap, int32_t *n)
+{
+    std::vector<mjk_class_timing> acc(kNumQuartetClasses);
+    for (int q = 0; q < kNumQuartetClasses; ++q) {
+        acc[q] = mjk_class_timing{};
+        acc[q].la = kClassTable[q].la;
+        acc[q].lb = kClassTable[q].lb;
+        acc[q].lc = kClassTable[q].lc;
+        acc[q].ld = kClassTable[q].ld;
+    }
+    for (size_t i = 0; i < gs.size(); ++i) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+        auto &t = acc[gs[i].qcls];
+        t.nlaunch += 1;
+        t.ms += ms;
+        t.nquartet += gs[i].nq;
+        t.nprim_quartet += gs[i].npq;
+        t.flops += grad ? gs[i].gcost : gs[i].cost;
+    }
+    int k = 0;
+    for (int q = 0; q < kNumQuartetClasses; ++q)
+        if (acc[q].nlaunch > 0) {
+            if (k < cap) out[k] = acc[q];
+            ++k;
+        }
+    *n = k;
+    return MJK_OK;
+}
+
+int check_qpl(const int32_t *qpl, int32_t n, const char *who)
+{
+    if (!qpl || n != kNumQuartetClasses)
+        return fail(MJK_ERR_INVALID_ARG, "%s: need %d per-class values", who, kNumQuartetClasses);
+    for (int q = 0; q < n; ++q) {
+        const int v = qpl[q];
+        if (v < 1 || v > kMaxQpl || (v & (v - 1)))
+            return fail(MJK_ERR_INVALID_ARG, "%s: class %d: %d quartets per lane (1, 2, 4, ... %d)", who, q, v,
+                        kMaxQpl);
+    }
+    return MJK_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int mjk_lmax(void) { return kLmax; }
+
+int mjk_num_classes(void) { return kNumQuartetClasses; }
+
+int mjk_class_l(int32_t q, int32_t *l4)
+{
+    if (q < 0 || q >= kNumQuartetClasses || !l4) return fail(MJK_ERR_INVALID_ARG, "mjk_class_l: bad argument");
+    l4[0] = kClassTable[q].la;
+    l4[1] = kClassTable[q].lb;
+    l4[2] = kClassTable[q].lc;
+    l4[3] = kClassTable[q].ld;
+    return MJK_OK;
+}
 
 const char *mjk_last_error(void) { return g_err.c_str(); }
 
@@ -176,6 +446,8 @@ int mjk_ctx_create(int device, mjk_ctx **out)
 }
 
 void mjk_ctx_destroy(mjk_ctx *ctx) { delete ctx; }
+
+}  // extern "C"
 
 static int validate_basis(const mjk_basis *b)
 {
@@ -207,17 +479,8 @@ static int validate_basis(const mjk_basis *b)
     return MJK_OK;
 }
 
-int mjk_nbf(const mjk_basis *basis, int64_t *nbf)
-{
-    if (!nbf) return fail(MJK_ERR_INVALID_ARG, "mjk_nbf: nbf is NULL");
-    if (int rc = validate_basis(basis)) return rc;
-    int64_t n = 0;
-    for (int s = 0; s < basis->nshell; ++s) n += ncart_h(basis->shell_l[s]);
-    *nbf = n;
-    return MJK_OK;
-}
-
-int mjk_plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts, mjk_plan **out, size_t *ws_bytes)
+static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts, bool in_batch, mjk_plan **out,
+                       size_t *ws_bytes)
 {
     if (!ctx || !out || !ws_bytes) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: NULL argument");
     *out = nullptr;
@@ -228,11 +491,14 @@ int mjk_plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts, m
         return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: schwarz_tau = %g", o.schwarz_tau);
     if (!(std::isfinite(o.fp32_tau) && o.fp32_tau >= 0.0))
         return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: fp32_tau = %g", o.fp32_tau);
-    if (o.flags & ~MJK_FLAG_CHECK) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: unknown flags 0x%x", o.flags);
+    if (o.flags & ~(MJK_FLAG_CHECK | MJK_FLAG_GRAD))
+        return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: unknown flags 0x%x", o.flags);
 
     auto *p = new mjk_plan;
     p->ctx = ctx;
     p->opts = o;
+    p->in_batch = in_batch;
+    for (int q = 0; q < kNumQuartetClasses; ++q) p->qpl[q] = 1;
     p->natom = b->natom;
     p->nshell = b->nshell;
     p->nprim = b->nprim;
@@ -302,18 +568,28 @@ int mjk_plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts, m
                 wl.bp = (int)p->bps.size();
                 wl.fp32 = prec;
                 wl.off = woff;
+                wl.nbra = p->bins[X].count;
+                wl.chunk = kChunk;
                 woff += 3 * (size_t)p->bins[X].count + 1;
                 p->lists.push_back(wl);
             }
             p->bps.push_back(bp);
         }
     p->work_ints = woff;
-    // split classes present: staging for one item per persistent block
+    // split classes present: staging for one item per persistent block;
+    // a launch never has more blocks than work items
     for (const auto &bp : p->bps) {
         const ClassEntry &ce = kClassTable[bp.qcls];
-        if (ce.split) p->stage_nacc = std::max(p->stage_nacc, (size_t)ce.nacc);
+        size_t need = ce.split ? (size_t)ce.nacc : 0;
+        if (o.flags & MJK_FLAG_GRAD) need = std::max(need, ce.grad_stage_nacc());
+        if (need == 0) continue;
+        p->stage_nacc = std::max(p->stage_nacc, need);
+        const int64_t ny = p->bins[bp.Y].count;
+        p->max_items = std::max(p->max_items, (int64_t)p->bins[bp.X].count * ((ny + kChunk - 1) / kChunk));
     }
-    p->nslot = p->stage_nacc ? kSlotsPerCU * std::max(1, ctx->ncu) : 0;
+    p->nslot = (p->stage_nacc && !in_batch)
+                   ? (int)std::min<int64_t>(kSlotsPerCU * std::max(1, ctx->ncu), 2 * p->max_items)
+                   : 0;
 
     // workspace layout
     size_t off = 0;
@@ -334,6 +610,8 @@ int mjk_plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts, m
     p->o_Q = take(sizeof(double) * p->npair);
     p->o_cls = take(sizeof(int32_t) * p->npair);
     p->o_work = take(sizeof(int32_t) * p->work_ints);
+    p->o_segs = take(in_batch ? 0 : sizeof(JKSeg) * p->lists.size());
+    p->o_queue = take(in_batch ? 0 : sizeof(uint32_t) * 2 * kNumQuartetClasses);
     p->o_eri = take(sizeof(EriItem) * kEriStage);
     p->o_stage = take(sizeof(double) * 64 * p->stage_nacc * (size_t)p->nslot);
     p->total = off;
@@ -349,17 +627,14 @@ int mjk_plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts, m
     return MJK_OK;
 }
 
-void mjk_plan_destroy(mjk_plan *plan) { delete plan; }
-
-int mjk_plan_bind(mjk_plan *p, void *workspace, size_t bytes, void *stream)
+// tables, Schwarz factors, sort and work lists of one plan (its workspace)
+static int plan_bind(mjk_plan *p, void *workspace, size_t bytes, hipStream_t s)
 {
-    if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_bind: plan is NULL");
     if (!workspace) return fail(MJK_ERR_WORKSPACE, "mjk_plan_bind: workspace is NULL");
     if (((uintptr_t)workspace & 255) != 0) return fail(MJK_ERR_WORKSPACE, "mjk_plan_bind: workspace not 256-byte aligned");
     if (bytes < p->total)
         return fail(MJK_ERR_WORKSPACE, "mjk_plan_bind: workspace %zu bytes < %zu needed", bytes, p->total);
     HIP_TRY(hipSetDevice(p->ctx->device));
-    hipStream_t s = (hipStream_t)stream;
     p->ws = (char *)workspace;
     p->bound = false;
     char *w = p->ws;
@@ -421,12 +696,11 @@ int mjk_plan_bind(mjk_plan *p, void *workspace, size_t bytes, void *stream)
 
     // stage 2: per bin pair, per bra, the kept ket prefix of the ket bin
     // (Q_AB Q_CD >= schwarz_tau), split into its FP64 prefix
-    // (Q_AB Q_CD >= fp32_tau) and FP32 remainder, each cut into chunks
+    // (Q_AB Q_CD >= fp32_tau) and FP32 remainder
     const double tau = p->opts.schwarz_tau, tau32 = p->opts.fp32_tau;
-    std::vector<int32_t> work(p->work_ints, 0);
+    p->work.assign(p->work_ints, 0);
     int64_t nq_kept = 0, nprimq = 0, ncart = 0, nq32 = 0;
-    double flops = 0.0;
-    int nlaunch = 0;
+    double flops = 0.0, gflops = 0.0;
     auto prefix_len = [&](const Bin &Y, double qb, double thr) {
         int lo = 0, hi = Y.count;  // first k with qb * Q_k < thr
         while (lo < hi) {
@@ -443,9 +717,8 @@ int mjk_plan_bind(mjk_plan *p, void *workspace, size_t bytes, void *stream)
         const BinPair &bp = p->bps[l64.bp];
         const Bin &X = p->bins[bp.X], &Y = p->bins[bp.Y];
         const ClassEntry &ce = kClassTable[bp.qcls];
-        int32_t *s64 = work.data() + l64.off, *e64 = s64 + X.count, *p64 = e64 + X.count;
-        int32_t *s32 = work.data() + l32.off, *e32 = s32 + X.count, *p32 = e32 + X.count;
-        p64[0] = p32[0] = 0;
+        int32_t *s64 = p->work.data() + l64.off, *e64 = s64 + X.count;
+        int32_t *s32 = p->work.data() + l32.off, *e32 = s32 + X.count;
         std::vector<int64_t> ynp(Y.count + 1, 0);  // prefix of K_C K_D over the ket bin
         for (int k = 0; k < Y.count; ++k) ynp[k + 1] = ynp[k] + psort[Y.begin + k].nprim;
         int64_t q64 = 0, q32 = 0, pq64 = 0, pq32 = 0;
@@ -458,8 +731,6 @@ int mjk_plan_bind(mjk_plan *p, void *workspace, size_t bytes, void *stream)
             e64[b] = c64;
             s32[b] = c64;
             e32[b] = keep;
-            p64[b + 1] = p64[b] + (c64 + kChunk - 1) / kChunk;
-            p32[b + 1] = p32[b] + (keep - c64 + kChunk - 1) / kChunk;
             const int64_t nb = psort[X.begin + b].nprim;
             q64 += c64;
             q32 += keep - c64;
@@ -469,58 +740,103 @@ int mjk_plan_bind(mjk_plan *p, void *workspace, size_t bytes, void *stream)
         const int nout = ncart_h(ce.la) * ncart_h(ce.lb) * ncart_h(ce.lc) * ncart_h(ce.ld);
         const int L = ce.la + ce.lb + ce.lc + ce.ld;
         const double fpq = ce.vrr_flops + prim_overhead_flops(L), fq = ce.hrr_flops + 12.0 * nout;
-        l64.nitems = p64[X.count];
+        const double gpq = ce.grad_vrr_flops + ce.grad_nup * prim_overhead_flops(L + 1) +
+                           ce.grad_ndown * (prim_overhead_flops(L - 1) + 1.0);
         l64.nq = q64;
         l64.npq = pq64;
         l64.cost = (double)pq64 * fpq + (double)q64 * fq;
-        l32.nitems = p32[X.count];
+        l64.gcost = (double)pq64 * gpq + (double)q64 * ce.grad_q_flops;
         l32.nq = q32;
         l32.npq = pq32;
         l32.cost = (double)pq32 * fpq + (double)q32 * fq;
+        l32.gcost = (double)pq32 * gpq + (double)q32 * ce.grad_q_flops;
         nq_kept += q64 + q32;
         nq32 += q32;
         nprimq += pq64 + pq32;
         ncart += (q64 + q32) * nout;
         flops += l64.cost + l32.cost;
-        nlaunch += (l64.nitems > 0) + (l32.nitems > 0);
+        gflops += l64.gcost + l32.gcost;
     }
-    if (!work.empty())
-        HIP_TRY(hipMemcpyAsync(w + p->o_work, work.data(), sizeof(int32_t) * work.size(), hipMemcpyHostToDevice, s));
-    // costliest launches first
-    std::stable_sort(p->lists.begin(), p->lists.end(),
-                     [](const WorkList &a, const WorkList &b) { return a.cost > b.cost; });
-    HIP_TRY(hipStreamSynchronize(s));  // host vectors above are released on return
+    rechunk(p, -1);
+    if (int rc = upload_work(p, s)) return rc;  // synchronizes: psort is released on return
     p->stats.nquartet_kept = nq_kept;
     p->stats.nquartet_fp32 = nq32;
     p->stats.nprim_quartet_kept = nprimq;
     p->stats.ncart_eri_kept = ncart;
     p->stats.vrr_flops_kept = flops;
-    p->stats.nlaunch = nlaunch + 3;
+    p->stats.grad_flops_kept = (p->opts.flags & MJK_FLAG_GRAD) ? gflops : 0.0;
+    if (!p->in_batch) {
+        p->groups = make_groups({p});
+        const int64_t zero = 0;
+        if (int rc = upload_groups(p->groups, {p}, &zero, (JKSeg *)(w + p->o_segs), s)) return rc;
+        p->stats.nlaunch = (int64_t)p->groups.size() + 4;
+    }
     p->bound = true;
     return MJK_OK;
 }
 
-static int check_density_host(const mjk_plan *p, const double *D)
+static int check_density_host(int64_t nbf, const double *D, const char *who)
 {
-    const size_t n = (size_t)p->nbf;
+    const size_t n = (size_t)nbf;
     std::vector<double> h(n * n);
     HIP_TRY(hipMemcpy(h.data(), D, sizeof(double) * n * n, hipMemcpyDeviceToHost));
     double mx = 0.0;
     for (double v : h) {
-        if (!std::isfinite(v)) return fail(MJK_ERR_INVALID_ARG, "mjk_build_jk: D has a non-finite entry");
+        if (!std::isfinite(v)) return fail(MJK_ERR_INVALID_ARG, "%s: D has a non-finite entry", who);
         mx = std::max(mx, std::fabs(v));
     }
     for (size_t i = 0; i < n; ++i)
         for (size_t j = 0; j < i; ++j)
             if (std::fabs(h[i * n + j] - h[j * n + i]) > 1e-12 * mx)
-                return fail(MJK_ERR_INVALID_ARG, "mjk_build_jk: D is not symmetric at (%zu, %zu)", i, j);
+                return fail(MJK_ERR_INVALID_ARG, "%s: D is not symmetric at (%zu, %zu)", who, i, j);
     return MJK_OK;
+}
+
+extern "C" {
+
+int mjk_nbf(const mjk_basis *basis, int64_t *nbf)
+{
+    if (!nbf) return fail(MJK_ERR_INVALID_ARG, "mjk_nbf: nbf is NULL");
+    if (int rc = validate_basis(basis)) return rc;
+    int64_t n = 0;
+    for (int s = 0; s < basis->nshell; ++s) n += ncart_h(basis->shell_l[s]);
+    *nbf = n;
+    return MJK_OK;
+}
+
+int mjk_plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts, mjk_plan **out, size_t *ws_bytes)
+{
+    return plan_create(ctx, b, opts, false, out, ws_bytes);
+}
+
+void mjk_plan_destroy(mjk_plan *plan) { delete plan; }
+
+int mjk_plan_bind(mjk_plan *p, void *workspace, size_t bytes, void *stream)
+{
+    if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_bind: plan is NULL");
+    if (p->in_batch) return fail(MJK_ERR_STATE, "mjk_plan_bind: plan belongs to a batch");
+    return plan_bind(p, workspace, bytes, (hipStream_t)stream);
+}
+
+int mjk_plan_set_tiles(mjk_plan *p, const int32_t *qpl, int32_t n)
+{
+    if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_set_tiles: plan is NULL");
+    if (!p->bound) return fail(MJK_ERR_STATE, "mjk_plan_set_tiles: plan is not bound");
+    if (int rc = check_qpl(qpl, n, "mjk_plan_set_tiles")) return rc;
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    HIP_TRY(hipDeviceSynchronize());  // no launch of this plan may still read the lists
+    for (int q = 0; q < n; ++q) p->qpl[q] = qpl[q];
+    rechunk(p, -1);
+    if (int rc = upload_work(p, nullptr)) return rc;
+    p->groups = make_groups({p});
+    const int64_t zero = 0;
+    return upload_groups(p->groups, {p}, &zero, (JKSeg *)(p->ws + p->o_segs), nullptr);
 }
 
 int mjk_build_jk(mjk_plan *p, const double *D, double *J, double *K, void *stream)
 {
     if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_build_jk: plan is NULL");
-    if (!p->bound) return fail(MJK_ERR_STATE, "mjk_build_jk: plan is not bound");
+    if (!p->bound || p->in_batch) return fail(MJK_ERR_STATE, "mjk_build_jk: plan is not bound");
     if (!D || !J || !K) return fail(MJK_ERR_INVALID_ARG, "mjk_build_jk: NULL matrix");
     if (J == K || (const double *)J == D || (const double *)K == D)
         return fail(MJK_ERR_INVALID_ARG, "mjk_build_jk: D, J, K must be distinct buffers");
@@ -528,50 +844,58 @@ int mjk_build_jk(mjk_plan *p, const double *D, double *J, double *K, void *strea
     hipStream_t s = (hipStream_t)stream;
     if (p->opts.flags & MJK_FLAG_CHECK) {
         HIP_TRY(hipStreamSynchronize(s));
-        if (int rc = check_density_host(p, D)) return rc;
+        if (int rc = check_density_host(p->nbf, D, "mjk_build_jk")) return rc;
     }
     const int64_t n2 = (int64_t)p->nbf * p->nbf;
     if (launch_fill(J, n2, 0.0, s) || launch_fill(K, n2, 0.0, s))
         return fail(MJK_ERR_HIP, "mjk_build_jk: fill launch failed");
     char *w = p->ws;
-    if (p->timing && p->ev.size() != 2 * p->lists.size()) {
-        for (auto e : p->ev) hipEventDestroy(e);
-        p->ev.assign(2 * p->lists.size(), nullptr);
-        for (auto &e : p->ev) HIP_TRY(hipEventCreate(&e));
-    }
+    if (p->timing)
+        if (int rc = ensure_events(p->ev, 2 * p->groups.size())) return rc;
     p->timed_last = p->timing;
-    for (size_t il = 0; il < p->lists.size(); ++il) {
-        const WorkList &wl = p->lists[il];
-        if (wl.nitems <= 0) continue;
-        const BinPair &bp = p->bps[wl.bp];
-        const Bin &X = p->bins[bp.X], &Y = p->bins[bp.Y];
-        const int32_t *wk = (const int32_t *)(w + p->o_work) + wl.off;
-        JKLaunch a{};
-        a.pairs = (const ShellPairD *)(w + p->o_psort);
-        a.prims = (const PrimPairD *)(w + p->o_prims);
-        a.D = D;
-        a.J = J;
-        a.K = K;
-        a.nbf = p->nbf;
-        a.bra_begin = X.begin;
-        a.nbra = X.count;
-        a.ket_begin = Y.begin;
-        a.same_bin = bp.X == bp.Y;
-        a.ket_start = wk;
-        a.ket_end = wk + X.count;
-        a.chunk_prefix = wk + 2 * X.count;
-        a.nitems = wl.nitems;
-        a.chunk = kChunk;
-        a.stage = (double *)(w + p->o_stage);
-        a.nslot = p->nslot;
-        const ClassEntry &ce = kClassTable[bp.qcls];
-        if (p->timing) HIP_TRY(hipEventRecord(p->ev[2 * il], s));
-        if ((wl.fp32 ? ce.jk32 : ce.jk)(a, s)) return fail(MJK_ERR_HIP, "mjk_build_jk: class launch failed");
-        if (p->timing) HIP_TRY(hipEventRecord(p->ev[2 * il + 1], s));
-    }
+    p->timed_grad = false;
+    if (int rc = run_groups(p->groups, (const JKSeg *)(w + p->o_segs), (uint32_t *)(w + p->o_queue),
+                            (double *)(w + p->o_stage), p->nslot, D, J, K, nullptr, 0, nullptr, s,
+                            p->timing ? &p->ev : nullptr, "mjk_build_jk"))
+        return rc;
     if (launch_symmetrize(J, p->nbf, s) || launch_symmetrize(K, p->nbf, s))
         return fail(MJK_ERR_HIP, "mjk_build_jk: symmetrize launch failed");
     return MJK_OK;
+}
+
+int mjk_e2(mjk_plan *p, const double *D, const double *J, const double *K, double *e2, void *stream)
+{
+    if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_e2: plan is NULL");
+    if (!D || !J || !K || !e2) return fail(MJK_ERR_INVALID_ARG, "mjk_e2: NULL argument");
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    if (launch_e2(D, J, K, p->nbf, e2, (hipStream_t)stream)) return fail(MJK_ERR_HIP, "mjk_e2: launch failed");
+    return MJK_OK;
+}
+
+int mjk_grad_e2(mjk_plan *p, const double *D, double *grad, void *stream)
+{
+    if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_grad_e2: plan is NULL");
+    if (!p->bound || p->in_batch) return fail(MJK_ERR_STATE, "mjk_grad_e2: plan is not bound");
+    if (!(p->opts.flags & MJK_FLAG_GRAD))
+        return fail(MJK_ERR_STATE, "mjk_grad_e2: plan was created without MJK_FLAG_GRAD");
+    if (!D || !grad) return fail(MJK_ERR_INVALID_ARG, "mjk_grad_e2: NULL argument");
+    if (p->natom > kGradMaxAtoms)
+        return fail(MJK_ERR_UNSUPPORTED, "mjk_grad_e2: %d atoms > %d", p->natom, kGradMaxAtoms);
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (p->opts.flags & MJK_FLAG_CHECK) {
+        HIP_TRY(hipStreamSynchronize(s));
+        if (int rc = check_density_host(p->nbf, D, "mjk_grad_e2")) return rc;
+    }
+    if (launch_fill(grad, 3 * (int64_t)p->natom, 0.0, s)) return fail(MJK_ERR_HIP, "mjk_grad_e2: fill failed");
+    char *w = p->ws;
+    if (p->timing)
+        if (int rc = ensure_events(p->ev, 2 * p->groups.size())) return rc;
+    p->timed_last = p->timing;
+    p->timed_grad = true;
+    return run_groups(p->groups, (const JKSeg *)(w + p->o_segs), (uint32_t *)(w + p->o_queue),
+                      (double *)(w + p->o_stage), p->nslot, D, nullptr, nullptr, grad, p->natom, nullptr, s,
+                      p->timing ? &p->ev : nullptr, "mjk_grad_e2");
 }
 
 int mjk_eri_class(mjk_plan *p, const int32_t *quartets, int64_t nq, double *out, int64_t out_len, void *stream)
@@ -657,42 +981,301 @@ int mjk_plan_set_timing(mjk_plan *p, int enable)
 int mjk_plan_timings(mjk_plan *p, mjk_class_timing *out, int32_t cap, int32_t *n)
 {
     if (!p || !n || (cap > 0 && !out)) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_timings: NULL argument");
-    if (!p->timed_last || p->ev.size() != 2 * p->lists.size())
+    if (!p->timed_last || p->ev.size() != 2 * p->groups.size())
         return fail(MJK_ERR_STATE, "mjk_plan_timings: the last build ran without timing");
-    std::vector<mjk_class_timing> acc(kNumQuartetClasses);
-    for (int q = 0; q < kNumQuartetClasses; ++q) {
-        acc[q] = mjk_class_timing{};
-        acc[q].la = kClassTable[q].la;
-        acc[q].lb = kClassTable[q].lb;
-        acc[q].lc = kClassTable[q].lc;
-        acc[q].ld = kClassTable[q].ld;
-    }
-    for (size_t il = 0; il < p->lists.size(); ++il) {
-        const auto &wl = p->lists[il];
-        if (wl.nitems <= 0) continue;
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, p->ev[2 * il], p->ev[2 * il + 1]));
-        auto &t = acc[p->bps[wl.bp].qcls];
-        t.nlaunch += 1;
-        t.ms += ms;
-        t.nquartet += wl.nq;
-        t.nprim_quartet += wl.npq;
-        t.flops += wl.cost;
-    }
-    int k = 0;
-    for (int q = 0; q < kNumQuartetClasses; ++q)
-        if (acc[q].nlaunch > 0) {
-            if (k < cap) out[k] = acc[q];
-            ++k;
-        }
-    *n = k;
-    return MJK_OK;
+    return fill_timings(p->groups, p->ev, p->timed_grad, out, cap, n);
 }
 
 int mjk_plan_stats_get(const mjk_plan *p, mjk_plan_stats *st)
 {
     if (!p || !st) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_stats_get: NULL argument");
     *st = p->stats;
+    return MJK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches: many molecules, one launch per (class, precision) over all of them
+// ---------------------------------------------------------------------------
+
+int mjk_batch_create(mjk_ctx *ctx, int32_t nmol, const mjk_basis *mols, const mjk_jk_opts *opts, mjk_batch **out,
+                     size_t *ws_bytes)
+{
+    if (!ctx || !mols || !out || !ws_bytes) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_create: NULL argument");
+    *out = nullptr;
+    if (nmol <= 0) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_create: nmol = %d", nmol);
+    if (opts && (opts->flags & MJK_FLAG_GRAD))
+        return fail(MJK_ERR_INVALID_ARG, "mjk_batch_create: batches build J and K only (no MJK_FLAG_GRAD)");
+    auto *bt = new mjk_batch;
+    bt->ctx = ctx;
+    for (int q = 0; q < kNumQuartetClasses; ++q) bt->qpl[q] = 1;
+    size_t off = 0;
+    int64_t moff = 0, max_items = 0;
+    bt->mat_off.push_back(0);
+    for (int m = 0; m < nmol; ++m) {
+        mjk_plan *p = nullptr;
+        size_t bytes = 0;
+        if (int rc = plan_create(ctx, &mols[m], opts, true, &p, &bytes)) {
+            delete bt;
+            char buf[600];
+            snprintf(buf, sizeof buf, "mjk_batch_create: molecule %d: %s", m, g_err.c_str());
+            g_err = buf;
+            return rc;
+        }
+        bt->plans.push_back(p);
+        bt->ws_off.push_back(off);
+        off = align_up(off + bytes);
+        moff += (int64_t)p->nbf * p->nbf;
+        bt->mat_off.push_back(moff);
+        bt->nseg += p->lists.size();
+        bt->stage_nacc = std::max(bt->stage_nacc, p->stage_nacc);
+        max_items += p->max_items;
+    }
+    bt->nslot = bt->stage_nacc ? (int)std::min<int64_t>(kSlotsPerCU * std::max(1, ctx->ncu), 2 * max_items) : 0;
+    auto take = [&](size_t bytes) {
+        const size_t o2 = off;
+        off = align_up(off + bytes);
+        return o2;
+    };
+    bt->o_segs = take(sizeof(JKSeg) * bt->nseg);
+    bt->o_queue = take(sizeof(uint32_t) * 2 * kNumQuartetClasses);
+    bt->o_stamps = take(sizeof(unsigned long long) * 2 * nmol);
+    bt->o_stage = take(sizeof(double) * 64 * bt->stage_nacc * (size_t)bt->nslot);
+    bt->total = off;
+    *ws_bytes = off;
+    *out = bt;
+    return MJK_OK;
+}
+
+void mjk_batch_destroy(mjk_batch *b) { delete b; }
+
+static int batch_regroup(mjk_batch *b, hipStream_t s)
+{
+    b->groups = make_groups(b->plans);
+    return upload_groups(b->groups, b->plans, b->mat_off.data(), (JKSeg *)(b->ws + b->o_segs), s);
+}
+
+int mjk_batch_bind(mjk_batch *b, void *workspace, size_t bytes, void *stream)
+{
+    if (!b) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_bind: batch is NULL");
+    if (!workspace) return fail(MJK_ERR_WORKSPACE, "mjk_batch_bind: workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0)
+        return fail(MJK_ERR_WORKSPACE, "mjk_batch_bind: workspace not 256-byte aligned");
+    if (bytes < b->total)
+        return fail(MJK_ERR_WORKSPACE, "mjk_batch_bind: workspace %zu bytes < %zu needed", bytes, b->total);
+    b->bound = false;
+    b->ws = (char *)workspace;
+    hipStream_t s = (hipStream_t)stream;
+    for (size_t m = 0; m < b->plans.size(); ++m) {
+        mjk_plan *p = b->plans[m];
+        for (int q = 0; q < kNumQuartetClasses; ++q) p->qpl[q] = b->qpl[q];
+        if (int rc = plan_bind(p, b->ws + b->ws_off[m], p->total, s)) return rc;
+    }
+    if (int rc = batch_regroup(b, s)) return rc;
+    b->bound = true;
+    return MJK_OK;
+}
+
+int mjk_batch_offsets(const mjk_batch *b, int64_t *mat_off)
+{
+    if (!b || !mat_off) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_offsets: NULL argument");
+    for (size_t m = 0; m < b->mat_off.size(); ++m) mat_off[m] = b->mat_off[m];
+    return MJK_OK;
+}
+
+int mjk_batch_set_tiles(mjk_batch *b, const int32_t *qpl, int32_t n)
+{
+    if (!b) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_set_tiles: batch is NULL");
+    if (!b->bound) return fail(MJK_ERR_STATE, "mjk_batch_set_tiles: batch is not bound");
+    if (int rc = check_qpl(qpl, n, "mjk_batch_set_tiles")) return rc;
+    HIP_TRY(hipSetDevice(b->ctx->device));
+    HIP_TRY(hipDeviceSynchronize());  // no launch of this batch may still read the lists
+    for (int q = 0; q < n; ++q) b->qpl[q] = qpl[q];
+    for (auto *p : b->plans) {
+        for (int q = 0; q < n; ++q) p->qpl[q] = qpl[q];
+        rechunk(p, -1);
+        if (int rc = upload_work(p, nullptr)) return rc;
+    }
+    return batch_regroup(b, nullptr);
+}
+
+int mjk_batch_set_stamps(mjk_batch *b, int enable)
+{
+    if (!b) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_set_stamps: batch is NULL");
+    b->stamps = enable != 0;
+    return MJK_OK;
+}
+
+int mjk_batch_set_timing(mjk_batch *b, int enable)
+{
+    if (!b) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_set_timing: batch is NULL");
+    b->timing = enable != 0;
+    return MJK_OK;
+}
+
+static int batch_run(mjk_batch *b, const double *D, double *J, double *K, hipStream_t s, bool timed)
+{
+    if (timed)
+        if (int rc = ensure_events(b->ev, 2 * b->groups.size())) return rc;
+    unsigned long long *st = nullptr;
+    if (b->stamps) {
+        st = (unsigned long long *)(b->ws + b->o_stamps);
+        if (launch_stamp_init(st, (int)b->plans.size(), s)) return fail(MJK_ERR_HIP, "mjk_batch_build_jk: stamp init");
+    }
+    b->stamped_last = b->stamps;
+    return run_groups(b->groups, (const JKSeg *)(b->ws + b->o_segs), (uint32_t *)(b->ws + b->o_queue),
+                      (double *)(b->ws + b->o_stage), b->nslot, D, J, K, nullptr, 0, st, s,
+                      timed ? &b->ev : nullptr, "mjk_batch_build_jk");
+}
+
+int mjk_batch_build_jk(mjk_batch *b, const double *D, double *J, double *K, void *stream)
+{
+    if (!b) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_build_jk: batch is NULL");
+    if (!b->bound) return fail(MJK_ERR_STATE, "mjk_batch_build_jk: batch is not bound");
+    if (!D || !J || !K) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_build_jk: NULL matrix");
+    if (J == K || (const double *)J == D || (const double *)K == D)
+        return fail(MJK_ERR_INVALID_ARG, "mjk_batch_build_jk: D, J, K must be distinct buffers");
+    HIP_TRY(hipSetDevice(b->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t tot = b->mat_off.back();
+    if (launch_fill(J, tot, 0.0, s) || launch_fill(K, tot, 0.0, s))
+        return fail(MJK_ERR_HIP, "mjk_batch_build_jk: fill launch failed");
+    b->timed_last = b->timing;
+    if (int rc = batch_run(b, D, J, K, s, b->timing)) return rc;
+    for (size_t m = 0; m < b->plans.size(); ++m) {
+        const int n = b->plans[m]->nbf;
+        if (launch_symmetrize(J + b->mat_off[m], n, s) || launch_symmetrize(K + b->mat_off[m], n, s))
+            return fail(MJK_ERR_HIP, "mjk_batch_build_jk: symmetrize launch failed");
+    }
+    return MJK_OK;
+}
+
+int mjk_batch_timings(mjk_batch *b, mjk_class_timing *out, int32_t cap, int32_t *n)
+{
+    if (!b || !n || (cap > 0 && !out)) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_timings: NULL argument");
+    if (!b->timed_last || b->ev.size() != 2 * b->groups.size())
+        return fail(MJK_ERR_STATE, "mjk_batch_timings: the last build ran without timing");
+    return fill_timings(b->groups, b->ev, false, out, cap, n);
+}
+
+int mjk_batch_mol_times(mjk_batch *b, double *ms)
+{
+    if (!b || !ms) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_mol_times: NULL argument");
+    if (!b->stamped_last) return fail(MJK_ERR_STATE, "mjk_batch_mol_times: the last build ran without stamps");
+    const size_t nm = b->plans.size();
+    std::vector<unsigned long long> h(2 * nm);
+    HIP_TRY(hipSetDevice(b->ctx->device));
+    HIP_TRY(hipMemcpy(h.data(), b->ws + b->o_stamps, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
+    int khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->ctx->device));
+    if (khz <= 0) return fail(MJK_ERR_HIP, "mjk_batch_mol_times: wall clock rate unknown");
+    unsigned long long t0 = ~0ull;
+    for (size_t m = 0; m < nm; ++m)
+        if (h[2 * m + 1] != 0) t0 = std::min(t0, h[2 * m]);
+    for (size_t m = 0; m < nm; ++m) {
+        if (h[2 * m + 1] == 0) {  // no work in this molecule
+            ms[2 * m] = ms[2 * m + 1] = 0.0;
+            continue;
+        }
+        ms[2 * m] = (double)(h[2 * m] - t0) / khz;
+        ms[2 * m + 1] = (double)(h[2 * m + 1] - t0) / khz;
+    }
+    return MJK_OK;
+}
+
+int mjk_batch_stats(const mjk_batch *b, mjk_plan_stats *total, int64_t *nq_per_mol)
+{
+    if (!b || !total) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_stats: NULL argument");
+    if (!b->bound) return fail(MJK_ERR_STATE, "mjk_batch_stats: batch is not bound");
+    mjk_plan_stats t{};
+    for (size_t m = 0; m < b->plans.size(); ++m) {
+        const mjk_plan_stats &s = b->plans[m]->stats;
+        t.nbf += s.nbf;
+        t.nshell += s.nshell;
+        t.npair += s.npair;
+        t.nprim_pair += s.nprim_pair;
+        t.nquartet_total += s.nquartet_total;
+        t.nquartet_kept += s.nquartet_kept;
+        t.nquartet_fp32 += s.nquartet_fp32;
+        t.nprim_quartet_kept += s.nprim_quartet_kept;
+        t.ncart_eri_kept += s.ncart_eri_kept;
+        t.vrr_flops_kept += s.vrr_flops_kept;
+        if (nq_per_mol) nq_per_mol[m] = s.nquartet_kept;
+    }
+    t.nlaunch = (int64_t)b->groups.size() + 2 + 2 * (int64_t)b->plans.size();
+    t.workspace_bytes = b->total;
+    *total = t;
+    return MJK_OK;
+}
+
+// Algorithm 2: every class starts at one quartet per lane; in each sweep a
+// class is timed, its workload doubled (Combine), timed again, and kept if
+// faster, else halved back (Revert); sweeps repeat while any class improved.
+// Times are the shortest of `reps` launches of that class alone.  J and K
+// hold no meaningful values afterwards.
+int mjk_batch_autotune(mjk_batch *b, const double *D, double *J, double *K, int32_t reps, int32_t *qpl_out,
+                       int32_t n, void *stream)
+{
+    if (!b) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_autotune: batch is NULL");
+    if (!b->bound) return fail(MJK_ERR_STATE, "mjk_batch_autotune: batch is not bound");
+    if (!D || !J || !K || !qpl_out || n != kNumQuartetClasses || reps < 1)
+        return fail(MJK_ERR_INVALID_ARG, "mjk_batch_autotune: bad argument");
+    HIP_TRY(hipSetDevice(b->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const bool stamps = b->stamps;
+    b->stamps = false;
+    std::vector<int32_t> qpl(kNumQuartetClasses, 1);
+    if (int rc = mjk_batch_set_tiles(b, qpl.data(), kNumQuartetClasses)) return rc;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    auto time_class = [&](int q, double &best) -> int {
+        std::vector<Group> sel;
+        for (const auto &g : b->groups)
+            if (g.qcls == q) sel.push_back(g);
+        best = 1e300;
+        for (int r = 0; r < reps; ++r) {
+            HIP_TRY(hipEventRecord(e0, s));
+            if (int rc = run_groups(sel, (const JKSeg *)(b->ws + b->o_segs), (uint32_t *)(b->ws + b->o_queue),
+                                    (double *)(b->ws + b->o_stage), b->nslot, D, J, K, nullptr, 0, nullptr, s,
+                                    nullptr, "mjk_batch_autotune"))
+                return rc;
+            HIP_TRY(hipEventRecord(e1, s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            best = std::min(best, (double)ms);
+        }
+        return MJK_OK;
+    };
+    std::vector<int> present;
+    for (const auto &g : b->groups)
+        if (std::find(present.begin(), present.end(), g.qcls) == present.end()) present.push_back(g.qcls);
+    std::vector<bool> done(kNumQuartetClasses, false);
+    bool improved = true;
+    int rc = MJK_OK;
+    while (improved && rc == MJK_OK) {
+        improved = false;
+        for (int q : present) {
+            if (done[q] || qpl[q] >= kMaxQpl) continue;
+            double t1 = 0.0, t2 = 0.0;
+            if ((rc = time_class(q, t1))) break;
+            qpl[q] *= 2;  // Combine
+            if ((rc = mjk_batch_set_tiles(b, qpl.data(), kNumQuartetClasses))) break;
+            if ((rc = time_class(q, t2))) break;
+            if (t2 < t1) {
+                improved = true;
+            } else {
+                qpl[q] /= 2;  // Revert
+                done[q] = true;
+                if ((rc = mjk_batch_set_tiles(b, qpl.data(), kNumQuartetClasses))) break;
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    b->stamps = stamps;
+    if (rc) return rc;
+    for (int q = 0; q < kNumQuartetClasses; ++q) qpl_out[q] = qpl[q];
     return MJK_OK;
 }
 

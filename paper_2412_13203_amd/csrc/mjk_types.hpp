@@ -17,7 +17,7 @@ struct alignas(16) PrimPairD {
     double P[3];     // (alpha A + beta B) / p
     double PA[3];    // P - A
     double K;
-    double pad;
+    double alpha;    // exponent of the first centre (derivative integrals)
 };
 static_assert(sizeof(PrimPairD) == 80, "PrimPairD layout");
 
@@ -43,22 +43,39 @@ struct alignas(16) EriItem {
     int32_t n1, n2, n3, n4;// caller's component counts (A, B, C, D)
 };
 
-struct JKLaunch {
-    const ShellPairD *pairs;   // class-sorted pair table
+// One segment of a class launch: the quartets of one (bra bin, ket bin) pair
+// of one molecule at one precision.  Work items of a launch are numbered
+// across its segments (item_begin); an item is one bra pair x `chunk` kets.
+struct alignas(16) JKSeg {
+    const ShellPairD *pairs;     // the molecule's class-sorted pair table
     const PrimPairD *prims;
-    const double *D;
+    const int32_t *ket_start;    // per bra: first ket (bin position)
+    const int32_t *ket_end;      // per bra: one past the last ket
+    const int32_t *chunk_prefix; // per bra: exclusive prefix of chunks (nbra + 1)
+    const int32_t *shell_atom;   // gradient: atom of each shell
+    int64_t mat_off;             // first element of this molecule's D, J, K
+    int32_t nbf, bra_begin, nbra, ket_begin;
+    int32_t same_bin;            // bra and ket bins coincide: keep ket <= bra
+    int32_t chunk;               // kets per item (multiple of 64)
+    int32_t item_begin;          // first launch item of this segment
+    int32_t mol;                 // molecule index
+    int32_t grad_off;            // gradient: first element of this molecule's gradient
+    int32_t natom;
+};
+
+struct JKLaunch {
+    const JKSeg *segs;           // device array, item_begin ascending
+    int32_t nseg;
+    int32_t nitems;              // items over all segments
+    const double *D;             // molecule m's matrices start at segs[].mat_off
     double *J;
     double *K;
-    int32_t nbf;
-    int32_t bra_begin, nbra, ket_begin;
-    int32_t same_bin;          // bra and ket bins coincide: keep ket <= bra
-    const int32_t *ket_start;  // per bra: first ket (bin position) of this list
-    const int32_t *ket_end;    // per bra: one past the last ket of this list
-    const int32_t *chunk_prefix; // per bra: exclusive prefix of ket chunks (nbra + 1)
-    int32_t nitems;            // chunk_prefix[nbra]
-    int32_t chunk;             // kets per work item (multiple of 64)
-    double *stage;             // split classes: per-slot staging of [e0|f0]
-    int32_t nslot;             // split classes: staging slots (persistent blocks)
+    double *grad;                // gradient launches only
+    double *stage;               // split classes: per-slot staging of [e0|f0]
+    int32_t nslot;               // split classes: staging slots (persistent blocks)
+    int32_t natom_max;           // gradient: LDS copy of one molecule's gradient
+    uint32_t *queue;             // persistent kernels: work counter, zero at launch
+    unsigned long long *stamps;  // optional: per molecule [first start, last end]
 };
 
 struct EriLaunch {
@@ -92,6 +109,13 @@ struct ClassEntry {
     JKFn jk32;         // FP32 recurrence / contraction, FP64 digestion
     EriFn eri;
     SchwarzFn schwarz;  // only on diagonal classes (la lb | la lb)
+    // nuclear gradient: shifted classes (d/dA, d/dB, d/dC raise or lower one
+    // centre), their staging need and algorithmic work
+    JKFn grad;
+    size_t (*grad_stage_nacc)();
+    double grad_vrr_flops;  // per primitive quartet, all shifted classes
+    int grad_nup, grad_ndown;  // shifted classes with L+1 and with L-1
+    double grad_q_flops;    // per contracted quartet: HRR + contraction with D
 };
 
 }  // namespace mjk

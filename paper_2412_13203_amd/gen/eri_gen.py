@@ -343,6 +343,9 @@ def cls_name(la, lb, lc, ld):
 
 # classes whose accumulators exceed this many doubles run as several passes
 MAX_ACC = int(os.environ.get("MJK_MAX_ACC", "96"))
+# the same for the shifted classes only the nuclear gradient uses (one unit
+# of angular momentum higher: more recurrence intermediates per target)
+GRAD_MAX_ACC = int(os.environ.get("MJK_GRAD_MAX_ACC", "64"))
 # a compiler scheduling fence every this many recurrence nodes keeps the
 # low-pressure emission order (0 = no fences)
 SCHED_WINDOW = int(os.environ.get("MJK_SCHED_WINDOW", "0"))
@@ -354,7 +357,7 @@ def fence(lines, count):
 
 
 class ClassCode:
-    def __init__(self, la, lb, lc, ld, max_acc=MAX_ACC):
+    def __init__(self, la, lb, lc, ld, max_acc=MAX_ACC, passes=False):
         self.la, self.lb, self.lc, self.ld = la, lb, lc, ld
         self.name = cls_name(la, lb, lc, ld)
         self.vrr = best_vrr(la, lb, lc, ld)
@@ -374,9 +377,15 @@ class ClassCode:
         self.nab, self.ncd = nab, ncd
         self.split = self.nacc > max_acc
         self.passes = []
+        # passes (and the cooperative HRR pieces) exist for split classes and,
+        # on request, as a single pass for a class that fits one lane
+        self.has_passes = self.split or passes
         if self.split:
             for tg in choose_passes(la, lb, lc, ld, max_acc):
                 self.passes.append((tg, best_vrr(la, lb, lc, ld, tg)))
+        elif passes:
+            self.passes.append((list(self.vrr.built_targets), self.vrr))
+        if self.has_passes:
             self.split_flops = sum(v.flops() for _, v in self.passes)
             # cooperative HRR: bra per ket column, then ket per (ab) row
             self.split_hrr_flops = 2 * (self.hb.count() * nF + nab * self.hk.count())
@@ -586,15 +595,16 @@ class ClassCode:
         la, lb, lc, ld = self.la, self.lb, self.lc, self.ld
         nb, nd = ncart(lb), ncart(ld)
         nF = len(self.fs)
-        L = ["template <typename T>",
+        L = ["template <int STRIDE, typename T>",
              f"__device__ __forceinline__ void hrr_bra_col_{self.name}(const T* __restrict__ ef, int f, const T AB[3], "
-             "T* __restrict__ abf)", "{"]
+             "T* __restrict__ abf)", "{",
+             "    // ef holds [e0|f0] as [e][f] with element stride STRIDE"]
         hb = self.hb
 
         def bname(key):
             node = hb.nodes[key]
             if node[0] == "base":
-                return f"ef[{self.eidx[node[1]] * nF} + f]"
+                return f"ef[({self.eidx[node[1]] * nF} + f) * STRIDE]"
             return f"b{node[6]}"
 
         for node in hb.order:
@@ -644,9 +654,9 @@ class ClassCode:
         lines.append("    __device__ static __forceinline__ void vrr(const T *F, const VrrGeom<T> &g, T *acc) {")
         lines.append("        " + " ".join(f"if constexpr (P == {k}) vrr_{self.name}_p{k}<T>(F, g, acc);"
                                            for k in range(P)) + " }")
-        lines.append("    template <typename T>")
+        lines.append("    template <int STRIDE, typename T>")
         lines.append("    __device__ static __forceinline__ void hrr_bra_col(const T *ef, int f, const T AB[3], T *abf)")
-        lines.append(f"    {{ hrr_bra_col_{self.name}<T>(ef, f, AB, abf); }}")
+        lines.append(f"    {{ hrr_bra_col_{self.name}<STRIDE, T>(ef, f, AB, abf); }}")
         lines.append("    template <typename T>")
         lines.append("    __device__ static __forceinline__ void hrr_ket_row(const T *row, const T CD[3], T *out)")
         lines.append(f"    {{ hrr_ket_row_{self.name}<T>(row, CD, out); }}")
@@ -658,7 +668,7 @@ class ClassCode:
             "class": self.name, "L": self.vrr.L, "nacc": self.nacc, "nout": self.nout,
             "vrr_nodes": len(self.vrr.order), "vrr_flops": self.vrr.flops(), "vrr_lambda": self.vrr.lam,
             "hrr_flops": self.hrr_flops, "hrr_bra_first": self.bra_first,
-            "split": self.split, "npass": len(self.passes),
+            "split": self.split, "npass": len(self.passes) if self.split else 0,
             "split_vrr_flops": self.split_flops if self.split else None,
         }
 
@@ -676,28 +686,62 @@ def quartet_classes(lmax):
     return out
 
 
+# Derivative integrals of a class, one shifted class per (centre, direction):
+# d/dA_i (ab|cd) = 2 alpha (a+1_i b|cd) - a_i (a-1_i b|cd), the same on B and
+# C; the fourth centre follows from translational invariance.
+GRAD_KINDS = ("A+", "A-", "B+", "B-", "C+", "C-")
+
+
+def grad_subclasses(la, lb, lc, ld):
+    out = []
+    for k, kind in enumerate(GRAD_KINDS):
+        cen, up = k // 2, kind[1] == "+"
+        t = [la, lb, lc, ld]
+        t[cen] += 1 if up else -1
+        if min(t) >= 0:
+            out.append((k, tuple(t)))
+    return out
+
+
+def grad_digest_flops(la, lb, lc, ld, k, sub):
+    """FMAs (2 flops) of contracting one shifted block with the density weights."""
+    cen, up = k // 2, GRAD_KINDS[k][1] == "+"
+    ls = list(sub)
+    nother = 1
+    for c in range(4):
+        if c != cen:
+            nother *= ncart(ls[c])
+    ndir = sum((sum(1 for x in t if x >= 1) if up else 3) for t in cart(ls[cen]))
+    return 2 * nother * ndir
+
+
 HEADER = """// Generated by paper_2412_13203_amd/gen/eri_gen.py -- do not edit.
-// Obara-Saika vertical and Head-Gordon-Pople horizontal recurrences per
+// Obara-Saika vertical and Head-Gordon-Pople horizontal recurrences of one
 // angular-momentum class; path chosen by the greedy search of Section 6.
 #pragma once
 """
 
 
-def emit_trait(cc):
+def emit_trait(cc, full):
     la, lb, lc, ld = cc.la, cc.lb, cc.lc, cc.ld
-    return "\n".join([
+    lines = [
         "template <>",
         f"struct EriClass<{la}, {lb}, {lc}, {ld}> {{",
         f"    static constexpr int NACC = {cc.nacc};",
         f"    static constexpr int NOUT = {cc.nout};",
-        "    template <typename T>",
-        "    __device__ static __forceinline__ void vrr(const T *F, const VrrGeom<T> &g, T *acc)",
-        f"    {{ vrr_{cc.name}<T>(F, g, acc); }}",
-        "    template <typename T>",
-        "    __device__ static __forceinline__ void hrr(const T *acc, const T AB[3], const T CD[3], T *out)",
-        f"    {{ hrr_{cc.name}<T>(acc, AB, CD, out); }}",
-        "};",
-    ])
+        f"    static constexpr bool SPLIT = {'true' if cc.split else 'false'};",
+    ]
+    if full:
+        lines += [
+            "    template <typename T>",
+            "    __device__ static __forceinline__ void vrr(const T *F, const VrrGeom<T> &g, T *acc)",
+            f"    {{ vrr_{cc.name}<T>(F, g, acc); }}",
+            "    template <typename T>",
+            "    __device__ static __forceinline__ void hrr(const T *acc, const T AB[3], const T CD[3], T *out)",
+            f"    {{ hrr_{cc.name}<T>(acc, AB, CD, out); }}",
+        ]
+    lines.append("};")
+    return "\n".join(lines)
 
 
 def _write(path, text):
@@ -707,65 +751,109 @@ def _write(path, text):
     os.replace(tmp, path)
 
 
-def generate(outdir, lmax=2):
-    """Write eri_classes.inc, one translation unit per class, dispatch.inc."""
-    os.makedirs(outdir, exist_ok=True)
-    infos = []
+def _class_job(args):
+    """Emit one class header; returns its name, text and counts."""
+    (la, lb, lc, ld), (fwd, grad) = args
+    cc = ClassCode(la, lb, lc, ld, max_acc=MAX_ACC if fwd else GRAD_MAX_ACC, passes=grad)
+    # a class the J/K path runs keeps its single-pass code (eri_class and
+    # Schwarz use it); a split class used only by the gradient needs passes
+    full = fwd or not cc.split
     body = [HEADER]
-    classes = quartet_classes(lmax)
-    ccs = []
-    for la, lb, lc, ld in classes:
-        cc = ClassCode(la, lb, lc, ld)
-        ccs.append(cc)
+    if full:
         body.append(cc.emit_vrr())
         body.append(cc.emit_hrr())
-        body.append(emit_trait(cc))
-        if cc.split:
-            for k in range(len(cc.passes)):
-                body.append(cc.emit_vrr_pass(k))
-            body.append(cc.emit_hrr_col_row())
-            body.append(cc.emit_split_trait())
-        infos.append(cc.info())
-    _write(os.path.join(outdir, "eri_classes.inc"), "\n\n".join(body) + "\n")
+    body.append(emit_trait(cc, full))
+    if cc.has_passes:
+        for k in range(len(cc.passes)):
+            body.append(cc.emit_vrr_pass(k))
+        body.append(cc.emit_hrr_col_row())
+        body.append(cc.emit_split_trait())
+    info = cc.info()
+    info["forward"] = fwd
+    return cc.name, "\n\n".join(body) + "\n", info
+
+
+def generate(outdir, lmax=2, jobs=None):
+    """Write one header per class (cls_<name>.inc), one translation unit per
+    J/K class and per gradient class, and dispatch.inc."""
+    os.makedirs(outdir, exist_ok=True)
+    fwd = quartet_classes(lmax)
+    need = {c: [True, False] for c in fwd}  # (J/K class, shifted class of a gradient)
+    for c in fwd:
+        for _, t in grad_subclasses(*c):
+            need.setdefault(t, [False, False])[1] = True
+    work = sorted(need.items(), key=lambda kv: -sum(kv[0]))
+    jobs = jobs or min(8, os.cpu_count() or 1)
+    if jobs > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(jobs) as pool:
+            res = pool.map(_class_job, work, chunksize=1)
+    else:
+        res = [_class_job(w) for w in work]
+    infos = {}
+    for (t, _), (name, text, info) in zip(work, res):
+        _write(os.path.join(outdir, f"cls_{name}.inc"), text)
+        infos[t] = info
     tus = []
-    for cc in ccs:
+    for c in fwd:
+        name = cls_name(*c)
+        split = infos[c]["split"]
         lines = ["// Generated by paper_2412_13203_amd/gen/eri_gen.py -- do not edit.",
-                 '#include "../kernels.hpp"', "namespace mjk {",
-                 (f"MJK_DEFINE_CLASS_SPLIT({cc.la}, {cc.lb}, {cc.lc}, {cc.ld}, {cc.name})" if cc.split else
-                  f"MJK_DEFINE_CLASS({cc.la}, {cc.lb}, {cc.lc}, {cc.ld}, {cc.name})")]
-        if (cc.la, cc.lb) == (cc.lc, cc.ld):
-            lines.append(f"MJK_DEFINE_SCHWARZ({cc.la}, {cc.lb}, {cc.name[:2]})")
+                 '#include "../kernels.hpp"', "namespace mjk {", f'#include "cls_{name}.inc"',
+                 (f"MJK_DEFINE_CLASS_SPLIT({c[0]}, {c[1]}, {c[2]}, {c[3]}, {name})" if split else
+                  f"MJK_DEFINE_CLASS({c[0]}, {c[1]}, {c[2]}, {c[3]}, {name})")]
+        if c[:2] == c[2:]:
+            lines.append(f"MJK_DEFINE_SCHWARZ({c[0]}, {c[1]}, {name[:2]})")
         lines.append("}  // namespace mjk")
-        path = os.path.join(outdir, f"tu_{cc.name}.hip")
+        path = os.path.join(outdir, f"tu_{name}.hip")
+        _write(path, "\n".join(lines) + "\n")
+        tus.append(path)
+        lines = ["// Generated by paper_2412_13203_amd/gen/eri_gen.py -- do not edit.",
+                 '#include "../kernels.hpp"', '#include "../grad_kernels.hpp"', "namespace mjk {"]
+        for _, t in grad_subclasses(*c):
+            lines.append(f'#include "cls_{cls_name(*t)}.inc"')
+        lines.append(f"MJK_DEFINE_GRAD({c[0]}, {c[1]}, {c[2]}, {c[3]}, {name})")
+        lines.append("}  // namespace mjk")
+        path = os.path.join(outdir, f"tu_grad_{name}.hip")
         _write(path, "\n".join(lines) + "\n")
         tus.append(path)
     # dispatch table, indexed by quartet class X(X+1)/2 + Y over pair classes
     d = ["// Generated by paper_2412_13203_amd/gen/eri_gen.py -- do not edit.", "#pragma once",
          '#include "../mjk_types.hpp"', "namespace mjk {"]
-    for cc in ccs:
-        d.append(f"int launch_jk_{cc.name}(const JKLaunch &, hipStream_t);")
-        d.append(f"int launch_jk32_{cc.name}(const JKLaunch &, hipStream_t);")
-        d.append(f"int launch_eri_{cc.name}(const EriLaunch &, hipStream_t);")
-        if (cc.la, cc.lb) == (cc.lc, cc.ld):
-            d.append(f"int launch_schwarz_{cc.name[:2]}(const SchwarzLaunch &, hipStream_t);")
+    for c in fwd:
+        name = cls_name(*c)
+        d.append(f"int launch_jk_{name}(const JKLaunch &, hipStream_t);")
+        d.append(f"int launch_jk32_{name}(const JKLaunch &, hipStream_t);")
+        d.append(f"int launch_eri_{name}(const EriLaunch &, hipStream_t);")
+        d.append(f"int launch_grad_{name}(const JKLaunch &, hipStream_t);")
+        d.append(f"size_t grad_stage_nacc_{name}();")
+        if c[:2] == c[2:]:
+            d.append(f"int launch_schwarz_{name[:2]}(const SchwarzLaunch &, hipStream_t);")
     d.append(f"constexpr int kLmax = {lmax};")
     d.append(f"constexpr int kNumPairClasses = {len(pair_classes(lmax))};")
-    d.append(f"constexpr int kNumQuartetClasses = {len(ccs)};")
+    d.append(f"constexpr int kNumQuartetClasses = {len(fwd)};")
     d.append("static const ClassEntry kClassTable[kNumQuartetClasses] = {")
-    for cc in ccs:
-        sch = f"launch_schwarz_{cc.name[:2]}" if (cc.la, cc.lb) == (cc.lc, cc.ld) else "nullptr"
+    for c in fwd:
+        name = cls_name(*c)
+        cc = infos[c]
+        sch = f"launch_schwarz_{name[:2]}" if c[:2] == c[2:] else "nullptr"
         # algorithmic work: the single-pass recurrence and the cheaper HRR order,
         # whatever the kernel executes (passes recompute shared intermediates)
-        vfl = cc.vrr.flops()
-        hfl = cc.hrr_flops
-        d.append(f"    {{{cc.la}, {cc.lb}, {cc.lc}, {cc.ld}, {cc.nacc}, {cc.nout}, {vfl}, "
-                 f"{hfl}, {int(cc.split)}, {len(cc.passes)}, launch_jk_{cc.name}, launch_jk32_{cc.name}, "
-                 f"launch_eri_{cc.name}, {sch}}},")
+        subs = grad_subclasses(*c)
+        g_vrr = sum(infos[t]["vrr_flops"] + 1 for _, t in subs)  # +1: the weight
+        g_up = sum(1 for k, _ in subs if GRAD_KINDS[k][1] == "+")
+        g_dn = len(subs) - g_up
+        nw = ncart(c[0]) * ncart(c[1]) * ncart(c[2]) * ncart(c[3])
+        g_q = sum(infos[t]["hrr_flops"] + grad_digest_flops(*c, k, t) for k, t in subs) + 6 * nw
+        d.append(f"    {{{c[0]}, {c[1]}, {c[2]}, {c[3]}, {cc['nacc']}, {cc['nout']}, {cc['vrr_flops']}, "
+                 f"{cc['hrr_flops']}, {int(cc['split'])}, {cc['npass']}, launch_jk_{name}, launch_jk32_{name}, "
+                 f"launch_eri_{name}, {sch}, launch_grad_{name}, grad_stage_nacc_{name}, {g_vrr}, {g_up}, {g_dn}, "
+                 f"{g_q}}},")
     d.append("};")
     d.append("}  // namespace mjk")
     _write(os.path.join(outdir, "dispatch.inc"), "\n".join(d) + "\n")
     with open(os.path.join(outdir, "opcount.json"), "w") as fh:
-        json.dump(infos, fh, indent=1)
+        json.dump([dict(v, tuple=list(k)) for k, v in sorted(infos.items())], fh, indent=1)
     return infos, tus
 
 
@@ -773,5 +861,5 @@ if __name__ == "__main__":
     out = sys.argv[1] if len(sys.argv) > 1 else "gen_out"
     lmax = int(sys.argv[2]) if len(sys.argv) > 2 else 2
     infos, tus = generate(out, lmax)
-    for i in infos:
-        print(i)
+    for k, i in sorted(infos.items()):
+        print(k, i)

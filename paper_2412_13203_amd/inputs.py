@@ -184,14 +184,14 @@ def make_config(i: int, seed: int | None = None, natom: int | None = None) -> di
             "name": f"config{i}", "seed": seed, "natom": na}
 
 
-def make_batch(nmol: int = 64, seed: int = 4, atom_range=(8, 96)) -> list:
+def make_batch(nmol: int = 64, seed: int = 4, atom_range=(8, 96), shells=(0, 0, 1, 2, 3)) -> list:
     """Workload 4: molecule m draws from default_rng([seed, m])."""
     mols = []
     for m in range(nmol):
         rng = np.random.default_rng([seed, m])
         na = int(rng.integers(atom_range[0], atom_range[1] + 1))
         xyz = _lattice(rng, na)
-        basis = make_basis(rng, xyz, (0, 0, 1, 2, 3), 0.08, 80.0, nprim_range=(1, 6))
+        basis = make_basis(rng, xyz, tuple(shells), 0.08, 80.0, nprim_range=(1, 6))
         n = basis["nbf"]
         D = density(rng, n, 2 * na, 1.0 / math.sqrt(n))
         mols.append({"basis": basis, "D": D, "tau": 1e-10, "natom": na})

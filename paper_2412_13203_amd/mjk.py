@@ -8,6 +8,7 @@ calls raise.
     plan = Plan(basis, tau=1e-10)          # mjk_plan_create + mjk_plan_bind
     J, K = plan.build_jk(D)                # mjk_build_jk
     blocks = plan.eri_class(quartets)      # mjk_eri_class
+    e = E2.apply(coords, D, basis)         # mjk_build_jk + mjk_e2; backward: mjk_grad_e2
 """
 from __future__ import annotations
 
@@ -24,6 +25,7 @@ MJK_OK = 0
 ERRORS = {-1: "MJK_ERR_INVALID_ARG", -2: "MJK_ERR_UNSUPPORTED", -3: "MJK_ERR_NO_DEVICE", -4: "MJK_ERR_WORKSPACE",
           -5: "MJK_ERR_HIP", -6: "MJK_ERR_STATE"}
 FLAG_CHECK = 0x1
+FLAG_GRAD = 0x2
 
 
 class MjkError(RuntimeError):
@@ -58,6 +60,7 @@ class PlanStats(ctypes.Structure):
         ("nquartet_fp32", ctypes.c_int64),
         ("nprim_quartet_kept", ctypes.c_int64), ("ncart_eri_kept", ctypes.c_int64), ("nlaunch", ctypes.c_int64),
         ("vrr_flops_kept", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t),
+        ("grad_flops_kept", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -78,9 +81,13 @@ class ClassTiming(ctypes.Structure):
 _lib = None
 
 # exported names of include/mjk.h
-EXPORTS = ["mjk_lmax", "mjk_last_error", "mjk_ctx_create", "mjk_ctx_destroy", "mjk_nbf", "mjk_plan_create",
-           "mjk_plan_bind", "mjk_build_jk", "mjk_eri_class", "mjk_schwarz", "mjk_plan_stats_get",
-           "mjk_plan_set_timing", "mjk_plan_timings", "mjk_plan_destroy"]
+EXPORTS = ["mjk_lmax", "mjk_num_classes", "mjk_class_l", "mjk_last_error", "mjk_ctx_create", "mjk_ctx_destroy",
+           "mjk_nbf", "mjk_plan_create", "mjk_plan_bind", "mjk_plan_set_tiles", "mjk_build_jk", "mjk_e2",
+           "mjk_grad_e2", "mjk_eri_class", "mjk_schwarz", "mjk_plan_stats_get", "mjk_plan_set_timing",
+           "mjk_plan_timings", "mjk_plan_destroy",
+           "mjk_batch_create", "mjk_batch_bind", "mjk_batch_offsets", "mjk_batch_build_jk", "mjk_batch_set_tiles",
+           "mjk_batch_autotune", "mjk_batch_set_stamps", "mjk_batch_mol_times", "mjk_batch_set_timing",
+           "mjk_batch_timings", "mjk_batch_stats", "mjk_batch_destroy"]
 
 
 def lib():
@@ -92,6 +99,23 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         L.mjk_lmax.restype = ctypes.c_int
+        L.mjk_num_classes.restype = ctypes.c_int
+        L.mjk_class_l.argtypes = [i32, ctypes.POINTER(i32)]
+        L.mjk_plan_set_tiles.argtypes = [vp, ctypes.POINTER(i32), i32]
+        L.mjk_batch_create.argtypes = [vp, i32, ctypes.POINTER(Basis), ctypes.POINTER(JKOpts), ctypes.POINTER(vp),
+                                       ctypes.POINTER(sz)]
+        L.mjk_batch_bind.argtypes = [vp, vp, sz, vp]
+        L.mjk_batch_offsets.argtypes = [vp, ctypes.POINTER(i64)]
+        L.mjk_batch_build_jk.argtypes = [vp, vp, vp, vp, vp]
+        L.mjk_batch_set_tiles.argtypes = [vp, ctypes.POINTER(i32), i32]
+        L.mjk_batch_autotune.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(i32), i32, vp]
+        L.mjk_batch_set_stamps.argtypes = [vp, ctypes.c_int]
+        L.mjk_batch_mol_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.mjk_batch_set_timing.argtypes = [vp, ctypes.c_int]
+        L.mjk_batch_timings.argtypes = [vp, ctypes.POINTER(ClassTiming), i32, ctypes.POINTER(i32)]
+        L.mjk_batch_stats.argtypes = [vp, ctypes.POINTER(PlanStats), ctypes.POINTER(i64)]
+        L.mjk_batch_destroy.argtypes = [vp]
+        L.mjk_batch_destroy.restype = None
         L.mjk_last_error.restype = ctypes.c_char_p
         L.mjk_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
         L.mjk_ctx_destroy.argtypes = [vp]
@@ -101,6 +125,8 @@ def lib():
                                       ctypes.POINTER(sz)]
         L.mjk_plan_bind.argtypes = [vp, vp, sz, vp]
         L.mjk_build_jk.argtypes = [vp, vp, vp, vp, vp]
+        L.mjk_e2.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.mjk_grad_e2.argtypes = [vp, vp, vp, vp]
         L.mjk_eri_class.argtypes = [vp, ctypes.POINTER(i32), i64, vp, i64, vp]
         L.mjk_schwarz.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.mjk_plan_stats_get.argtypes = [vp, ctypes.POINTER(PlanStats)]
@@ -160,8 +186,11 @@ def _stream(torch, device):
 class Plan:
     """A bound plan: tables for one basis/geometry in a torch-owned workspace."""
 
-    def __init__(self, basis: dict, tau: float = 0.0, flags: int = 0, device: int = 0, fp32_tau: float = 0.0):
+    def __init__(self, basis: dict, tau: float = 0.0, flags: int = 0, device: int = 0, fp32_tau: float = 0.0,
+                 grad: bool = False):
         import torch
+        if grad:
+            flags |= FLAG_GRAD
         self.torch = torch
         self.device = device
         self.basis = basis
@@ -204,6 +233,33 @@ class Plan:
                                   ctypes.c_void_p(K.data_ptr()), _stream(torch, self.device)))
         return J, K
 
+    def _dev_matrix(self, M, name):
+        torch = self.torch
+        n = self.nbf
+        if not (torch.is_tensor(M) and M.dtype == torch.float64 and M.is_contiguous()
+                and M.device == torch.device(f"cuda:{self.device}") and M.shape == (n, n)):
+            raise MjkError(-1, f"{name} must be a contiguous float64 ({n}, {n}) tensor on cuda:{self.device}")
+        return ctypes.c_void_p(M.data_ptr())
+
+    def e2(self, D, J, K, out=None):
+        """E2 = 1/2 Tr(DJ) - 1/4 Tr(DK) as a 0-d device tensor (mjk_e2)."""
+        torch = self.torch
+        if out is None:
+            out = torch.empty((), dtype=torch.float64, device=f"cuda:{self.device}")
+        _check(lib().mjk_e2(self._p, self._dev_matrix(D, "D"), self._dev_matrix(J, "J"), self._dev_matrix(K, "K"),
+                            ctypes.c_void_p(out.data_ptr()), _stream(torch, self.device)))
+        return out
+
+    def grad_e2(self, D, out=None):
+        """dE2/dR at fixed D, (natom, 3) float64 on the plan's device (mjk_grad_e2)."""
+        torch = self.torch
+        natom = self._hb.xyz.shape[0]
+        if out is None:
+            out = torch.empty((natom, 3), dtype=torch.float64, device=f"cuda:{self.device}")
+        _check(lib().mjk_grad_e2(self._p, self._dev_matrix(D, "D"), ctypes.c_void_p(out.data_ptr()),
+                                 _stream(torch, self.device)))
+        return out
+
     def eri_class(self, quartets):
         """Contracted ERI blocks for shell quartets (nq x 4), as a list of (na,nb,nc,nd) tensors."""
         torch = self.torch
@@ -219,6 +275,11 @@ class Plan:
             res.append(out[o:o + s].view(int(nc[a]), int(nc[b]), int(nc[c]), int(nc[d])))
             o += s
         return res
+
+    def set_tiles(self, qpl):
+        """Quartets per lane per class (mjk_plan_set_tiles); qpl: sequence of num_classes() ints."""
+        arr = (ctypes.c_int32 * len(qpl))(*[int(v) for v in qpl])
+        _check(lib().mjk_plan_set_tiles(self._p, arr, len(qpl)))
 
     def set_timing(self, enable: bool = True):
         _check(lib().mjk_plan_set_timing(self._p, int(bool(enable))))
@@ -236,6 +297,175 @@ class Plan:
         Q = np.zeros((ns, ns))
         _check(lib().mjk_schwarz(self._p, Q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return Q
+
+
+def num_classes() -> int:
+    return int(lib().mjk_num_classes())
+
+
+def class_names():
+    """Quartet class names ("ssss", "psss", ...) in the library's class order."""
+    out = []
+    l4 = (ctypes.c_int32 * 4)()
+    for q in range(num_classes()):
+        _check(lib().mjk_class_l(q, l4))
+        out.append("".join("spdfg"[l4[i]] for i in range(4)))
+    return out
+
+
+class Batch:
+    """Many molecules in one launch per class (mjk_batch_*).  D, J, K of
+    molecule m are views into one packed device buffer (offsets())."""
+
+    def __init__(self, bases, tau: float = 0.0, device: int = 0, fp32_tau: float = 0.0):
+        import torch
+        self.torch = torch
+        self.device = device
+        self._hbs = [_HostBasis(b) for b in bases]
+        n = len(self._hbs)
+        arr = (Basis * n)(*[h.s for h in self._hbs])
+        opts = JKOpts(float(tau), float(fp32_tau), 0)
+        p = ctypes.c_void_p()
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().mjk_batch_create(context(device), n, arr, ctypes.byref(opts), ctypes.byref(p),
+                                      ctypes.byref(nbytes)))
+        self._b = p
+        self.nmol = n
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=f"cuda:{device}")
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        _check(lib().mjk_batch_bind(p, ctypes.c_void_p(aligned), ctypes.c_size_t(int(nbytes.value)),
+                                    _stream(torch, device)))
+        off = (ctypes.c_int64 * (n + 1))()
+        _check(lib().mjk_batch_offsets(p, off))
+        self.mat_off = [int(off[i]) for i in range(n + 1)]
+        self.nbf = [int(h.ncart.sum()) for h in self._hbs]
+        st = PlanStats()
+        nq = (ctypes.c_int64 * n)()
+        _check(lib().mjk_batch_stats(p, ctypes.byref(st), nq))
+        self.stats = st.as_dict()
+        self.nq_per_mol = [int(nq[i]) for i in range(n)]
+
+    def __del__(self):
+        b = getattr(self, "_b", None)
+        if b is not None and b.value and _lib is not None:
+            _lib.mjk_batch_destroy(b)
+            self._b = None
+
+    def pack(self, Ds):
+        """One packed float64 device buffer from per-molecule matrices."""
+        torch = self.torch
+        buf = torch.empty(self.mat_off[-1], dtype=torch.float64, device=f"cuda:{self.device}")
+        for m, D in enumerate(Ds):
+            buf[self.mat_off[m]:self.mat_off[m + 1]] = torch.as_tensor(
+                D, dtype=torch.float64, device=buf.device).reshape(-1)
+        return buf
+
+    def unpack(self, buf):
+        return [buf[self.mat_off[m]:self.mat_off[m + 1]].view(self.nbf[m], self.nbf[m]) for m in range(self.nmol)]
+
+    def _buf(self, x, name):
+        torch = self.torch
+        if not (torch.is_tensor(x) and x.dtype == torch.float64 and x.is_contiguous() and x.numel() == self.mat_off[-1]
+                and x.device == torch.device(f"cuda:{self.device}")):
+            raise MjkError(-1, f"{name} must be a packed contiguous float64 tensor of {self.mat_off[-1]} elements")
+        return ctypes.c_void_p(x.data_ptr())
+
+    def build_jk(self, D, J=None, K=None):
+        """Packed J, K for the packed density D (mjk_batch_build_jk)."""
+        torch = self.torch
+        if J is None:
+            J = torch.empty_like(D)
+        if K is None:
+            K = torch.empty_like(D)
+        _check(lib().mjk_batch_build_jk(self._b, self._buf(D, "D"), self._buf(J, "J"), self._buf(K, "K"),
+                                        _stream(torch, self.device)))
+        return J, K
+
+    def set_tiles(self, qpl):
+        arr = (ctypes.c_int32 * len(qpl))(*[int(v) for v in qpl])
+        _check(lib().mjk_batch_set_tiles(self._b, arr, len(qpl)))
+
+    def autotune(self, D, reps: int = 2):
+        """Algorithm 2 on this batch; returns the chosen quartets-per-lane table (left active)."""
+        torch = self.torch
+        J = torch.empty_like(D)
+        K = torch.empty_like(D)
+        n = num_classes()
+        out = (ctypes.c_int32 * n)()
+        _check(lib().mjk_batch_autotune(self._b, self._buf(D, "D"), self._buf(J, "J"), self._buf(K, "K"), int(reps),
+                                        out, n, _stream(torch, self.device)))
+        return [int(out[i]) for i in range(n)]
+
+    def set_stamps(self, enable: bool = True):
+        _check(lib().mjk_batch_set_stamps(self._b, int(bool(enable))))
+
+    def mol_times(self):
+        """(start_ms, end_ms) per molecule of the last build, from the earliest start."""
+        ms = (ctypes.c_double * (2 * self.nmol))()
+        _check(lib().mjk_batch_mol_times(self._b, ms))
+        return [(ms[2 * m], ms[2 * m + 1]) for m in range(self.nmol)]
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().mjk_batch_set_timing(self._b, int(bool(enable))))
+
+    def timings(self):
+        cap = 256
+        arr = (ClassTiming * cap)()
+        n = ctypes.c_int32(0)
+        _check(lib().mjk_batch_timings(self._b, arr, cap, ctypes.byref(n)))
+        return [arr[i].as_dict() for i in range(min(n.value, cap))]
+
+
+_E2 = None
+
+
+def _e2_function():
+    """torch.autograd.Function E2(coords, D, basis, tau=0, device=0).
+
+    forward: plan for the basis at `coords` (natom x 3, bohr), J and K
+    (mjk_build_jk), E2 = 1/2 Tr(DJ) - 1/4 Tr(DK) (mjk_e2).
+    backward: dE2/dcoords = mjk_grad_e2 at fixed D; dE2/dD = J - K/2 (the
+    derivative of E2 with respect to a symmetric D's entries, taken as
+    independent).  The upstream gradient scales both (chain rule)."""
+    global _E2
+    if _E2 is not None:
+        return _E2
+    import torch
+
+    class E2(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, coords, D, basis, tau=0.0, device=0):
+            b = dict(basis)
+            b["xyz"] = coords.detach().to("cpu", torch.float64).numpy().reshape(-1, 3)
+            plan = Plan(b, tau=tau, device=device, grad=True)
+            Dd = D.detach().to(f"cuda:{device}", torch.float64).contiguous()
+            J, K = plan.build_jk(Dd)
+            e = plan.e2(Dd, J, K)
+            ctx.plan = plan
+            ctx.coords_meta = (coords.shape, coords.dtype, coords.device)
+            ctx.save_for_backward(Dd, J, K)
+            return e.to(D.device) if D.device != e.device else e
+
+        @staticmethod
+        def backward(ctx, g):
+            Dd, J, K = ctx.saved_tensors
+            shape, dtype, dev = ctx.coords_meta
+            gc = gD = None
+            g = g.to(Dd.device)
+            if ctx.needs_input_grad[0]:
+                gc = (ctx.plan.grad_e2(Dd) * g).reshape(shape).to(dev, dtype)
+            if ctx.needs_input_grad[1]:
+                gD = (J - 0.5 * K) * g
+            return gc, gD, None, None, None
+
+    _E2 = E2
+    return E2
+
+
+def __getattr__(name):
+    if name == "E2":
+        return _e2_function()
+    raise AttributeError(name)
 
 
 def build_jk(basis: dict, D, tau: float = 0.0, device: int = 0):

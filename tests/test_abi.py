@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "mjk.h")).read()
-    return sorted(set(re.findall(r"\b(mjk_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(mjk_[a-z_0-9]+)\s*\(", src)))
 
 
 def test_exports_every_declared_function():
