@@ -1,6 +1,7 @@
 """Benchmark: J/K build throughput (unique shell quartets / s) on one MI355X.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline] [--no-mixed] [--no-grad]
+                    [--no-batch]
 
 Workload: 40 atoms on a jittered cubic lattice (2.5 bohr, +-0.3), shells
 s, s, p, d per atom with 3 primitives each (440 Cartesian functions), Schwarz
@@ -14,7 +15,9 @@ with HIP events on the launch stream during the timed steps; `cpu_baseline`
 times the plain FP64 CPU oracle on a bounded sample of the same workload.
 `mixed`: the 120-atom workload built in FP64 and in mixed precision (speedup,
 E2 difference).  `grad`: the 60-atom workload's forward (J/K + E2) and
-backward (nuclear gradient) times.
+backward (nuclear gradient) times.  `batch`: 64 molecules of 8-32 atoms
+(K ~ U{1..6}) built one molecule at a time and as one batch with autotuned
+tiles; per-molecule times come from in-kernel wall-clock stamps.
 """
 import argparse
 import json
@@ -29,6 +32,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "J/K build ERI quartets/s + speedup vs FP64 GPU path at ≤1e-6 Eh error"
 FP64_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_jk_40atom_spd.json")
+
+
+def kernel_source_hash(cls):
+    """Hash of the sources a class kernel is built from (its generated class
+    code, the kernel templates, the record layouts and the Boys table)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2412_13203_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "mjk_types.hpp", os.path.join("gen", "boys_table.inc"),
+              os.path.join("gen", f"cls_{cls}.inc")):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of class `cls` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE record, if it was taken on the current sources."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))["classes"][cls]
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash(cls):
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
 
 
 def cpu_baseline(cfg, target_s=15.0):
@@ -165,6 +196,78 @@ def grad_comparison(torch, mjk, inputs, dev, steps=2, warmup=1):
     }
 
 
+def batch_comparison(torch, mjk, inputs, dev, nmol=64, atom_range=(8, 32), steps=2):
+    """Many molecules of uneven size: sequential single-molecule FP64 builds
+    (default tiles) vs one batch (one launch per class over all molecules),
+    with default tiles and with the tiles Algorithm 2 picks on this batch."""
+    shells = (0, 0, 1, 2, 3) if mjk.lib().mjk_lmax() >= 3 else (0, 0, 1, 2)
+    mols = inputs.make_batch(nmol=nmol, seed=4, atom_range=atom_range, shells=shells)
+    tau = mols[0]["tau"]
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    # sequential: one plan per molecule, plans built before timing
+    plans = [mjk.Plan(m["basis"], tau=tau, device=dev) for m in mols]
+    Ds = [torch.as_tensor(m["D"], device=f"cuda:{dev}") for m in mols]
+    outs = [(torch.empty_like(D), torch.empty_like(D)) for D in Ds]
+    for p, D, (J, K) in zip(plans, Ds, outs):
+        p.build_jk(D, J, K)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(steps):
+        for p, D, (J, K) in zip(plans, Ds, outs):
+            p.build_jk(D, J, K)
+    ev1.record()
+    torch.cuda.synchronize()
+    seq_ms = ev0.elapsed_time(ev1) / steps
+    nq = sum(p.stats["nquartet_kept"] for p in plans)
+    del plans, outs
+    t0 = time.time()
+    bt = mjk.Batch([m["basis"] for m in mols], tau=tau, device=dev)
+    torch.cuda.synchronize()
+    plan_ms = (time.time() - t0) * 1e3
+    D = bt.pack([m["D"] for m in mols])
+    J = torch.empty_like(D)
+    K = torch.empty_like(D)
+
+    def timed():
+        bt.build_jk(D, J, K)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(steps):
+            bt.build_jk(D, J, K)
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps
+
+    default_ms = timed()
+    t0 = time.time()
+    qpl = bt.autotune(D, reps=2)
+    tune_s = time.time() - t0
+    tuned_ms = timed()
+    bt.set_stamps(True)
+    bt.build_jk(D, J, K)
+    torch.cuda.synchronize()
+    times = [t for t, n in zip(bt.mol_times(), bt.nq_per_mol) if n > 0]
+    dur = sorted(t1 - t0_ for t0_, t1 in times)
+    ends = sorted(t1 for _, t1 in times)
+    names = mjk.class_names()
+    print(f"bench: batch of {nmol}: sequential {seq_ms:.1f} ms, batch {default_ms:.1f} ms, tuned {tuned_ms:.1f} ms",
+          file=sys.stderr, flush=True)
+    return {
+        "workload": f"{nmol} jittered-lattice molecules, atoms ~ U{{{atom_range[0]}..{atom_range[1]}}}, shells "
+                    f"{','.join('spdf'[l] for l in shells)}, K ~ U{{1..6}}, Schwarz {tau:g}, FP64",
+        "nmol": nmol, "nbf_total": int(sum(bt.nbf)), "quartets": bt.stats["nquartet_kept"],
+        "prim_quartets": bt.stats["nprim_quartet_kept"], "plan_ms": plan_ms,
+        "sequential_ms": seq_ms, "sequential_quartets_per_s": nq / (seq_ms * 1e-3),
+        "batch_default_ms": default_ms, "batch_tuned_ms": tuned_ms,
+        "batch_quartets_per_s": bt.stats["nquartet_kept"] / (tuned_ms * 1e-3),
+        "speedup_vs_sequential": seq_ms / tuned_ms, "autotune_s": tune_s,
+        "tuned_quartets_per_lane": {names[q]: v for q, v in enumerate(qpl) if v != 1},
+        "per_molecule_ms": {"min": dur[0], "median": dur[len(dur) // 2], "max": dur[-1]},
+        "finish_spread_ms": ends[-1] - ends[0],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +279,8 @@ def main():
                          "speedup over the FP64 path and E2 difference)")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the 60-atom nuclear-gradient timing (backward / forward ratio)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-molecule batched build (one launch per class, autotuned tiles)")
     ap.add_argument("--fp32-tau", type=float, nargs="+", default=[1e-4],
                     help="mixed-precision thresholds for --mixed (first one is the headline)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -295,7 +400,7 @@ def main():
         "algorithmic_tflops": total_flops / (ms_per_step * 1e-3) / 1e12,
         "fp64_frac_whole_step": total_flops / (ms_per_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
         "roofline": {"bound": "alu", "kernel": f"k_jk<{dom_cls}>", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(dom_cls),
                      "avg_launch_ms": avg_ms, "flops_per_launch": flops_per_launch},
         "classes": classes,
         "parity_vs_stored_oracle_blocks": {"max_abs_dJ": dj, "max_abs_dK": dk},
@@ -304,6 +409,8 @@ def main():
         out["mixed"] = mixed_comparison(torch, mjk, inputs, dev, taus=args.fp32_tau)
     if not args.no_grad:
         out["grad"] = grad_comparison(torch, mjk, inputs, dev)
+    if not args.no_batch:
+        out["batch"] = batch_comparison(torch, mjk, inputs, dev)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)
