@@ -176,7 +176,10 @@ int mjk_plan_set_tiles(mjk_plan *plan, const int32_t *qpl, int32_t n);
  * quartets: host int32, nq x 4 shell indices (A, B, C, D) in any order.
  * out: device float64; quartet q occupies na*nb*nc*nd values, row-major over
  * (a, b, c, d) in the caller's shell order, blocks back to back in request
- * order; out_len must equal the total.  No screening is applied. */
+ * order; out_len must equal the total.  No screening is applied; the plan's
+ * fp32_tau is: a quartet with Q_AB Q_CD < fp32_tau runs its vertical
+ * recurrence and contraction in FP32 as in mjk_build_jk, so that the FP32
+ * error of single integrals can be measured. */
 int mjk_eri_class(mjk_plan *plan, const int32_t *quartets, int64_t nq, double *out, int64_t out_len,
                   void *stream);
 

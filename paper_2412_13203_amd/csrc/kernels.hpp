@@ -399,9 +399,10 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
 
 // ---------------------------------------------------------------------------
 // Explicit ERI blocks: one requested quartet per lane, canonical class order,
-// written back in the caller's shell order.
+// written back in the caller's shell order.  T = float: FP32 recurrence and
+// contraction, HRR on the widened values (as in the J/K path).
 // ---------------------------------------------------------------------------
-template <int LA, int LB, int LC, int LD>
+template <int LA, int LB, int LC, int LD, typename T>
 __global__ __launch_bounds__(64) void k_eri(EriLaunch a)
 {
     using C = EriClass<LA, LB, LC, LD>;
@@ -411,10 +412,17 @@ __global__ __launch_bounds__(64) void k_eri(EriLaunch a)
     const EriItem it = a.items[t];
     const ShellPairD bra = a.pairs[it.bra];
     const ShellPairD ket = a.pairs[it.ket];
-    double acc[C::NACC];
-    contract_quartet<LA, LB, LC, LD, double>(bra, ket, a.prims, true, acc);
+    T acc[C::NACC];
+    contract_quartet<LA, LB, LC, LD, T>(bra, ket, a.prims, true, acc);
     double eri[C::NOUT];
-    C::template hrr<double>(acc, bra.AB, ket.AB, eri);
+    if constexpr (sizeof(T) == sizeof(double)) {
+        C::template hrr<double>(acc, bra.AB, ket.AB, eri);
+    } else {
+        double acc64[C::NACC];
+#pragma unroll
+        for (int i = 0; i < C::NACC; ++i) acc64[i] = (double)acc[i];
+        C::template hrr<double>(acc64, bra.AB, ket.AB, eri);
+    }
     const bool sab = it.flags & 1, scd = it.flags & 2, sbk = it.flags & 4;
     double *out = a.out + it.out_off;
     for (int i = 0; i < NA; ++i)
@@ -716,7 +724,13 @@ int launch_plain(const JKLaunch &a, hipStream_t s)
     int launch_eri_##NAME(const EriLaunch &a, hipStream_t s)                                       \
     {                                                                                               \
         if (a.n <= 0) return 0;                                                                     \
-        hipLaunchKernelGGL((k_eri<LA, LB, LC, LD>), dim3((a.n + 63) / 64), dim3(64), 0, s, a);      \
+        hipLaunchKernelGGL((k_eri<LA, LB, LC, LD, double>), dim3((a.n + 63) / 64), dim3(64), 0, s, a); \
+        return hipGetLastError() == hipSuccess ? 0 : -1;                                            \
+    }                                                                                               \
+    int launch_eri32_##NAME(const EriLaunch &a, hipStream_t s)                                     \
+    {                                                                                               \
+        if (a.n <= 0) return 0;                                                                     \
+        hipLaunchKernelGGL((k_eri<LA, LB, LC, LD, float>), dim3((a.n + 63) / 64), dim3(64), 0, s, a); \
         return hipGetLastError() == hipSuccess ? 0 : -1;                                            \
     }
 
@@ -732,7 +746,13 @@ int launch_plain(const JKLaunch &a, hipStream_t s)
     int launch_eri_##NAME(const EriLaunch &a, hipStream_t s)                                       \
     {                                                                                               \
         if (a.n <= 0) return 0;                                                                     \
-        hipLaunchKernelGGL((k_eri<LA, LB, LC, LD>), dim3((a.n + 63) / 64), dim3(64), 0, s, a);      \
+        hipLaunchKernelGGL((k_eri<LA, LB, LC, LD, double>), dim3((a.n + 63) / 64), dim3(64), 0, s, a); \
+        return hipGetLastError() == hipSuccess ? 0 : -1;                                            \
+    }                                                                                               \
+    int launch_eri32_##NAME(const EriLaunch &a, hipStream_t s)                                     \
+    {                                                                                               \
+        if (a.n <= 0) return 0;                                                                     \
+        hipLaunchKernelGGL((k_eri<LA, LB, LC, LD, float>), dim3((a.n + 63) / 64), dim3(64), 0, s, a); \
         return hipGetLastError() == hipSuccess ? 0 : -1;                                            \
     }
 

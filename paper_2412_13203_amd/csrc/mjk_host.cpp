@@ -904,8 +904,9 @@ int mjk_eri_class(mjk_plan *p, const int32_t *quartets, int64_t nq, double *out,
     if (!p->bound) return fail(MJK_ERR_STATE, "mjk_eri_class: plan is not bound");
     if (nq < 0 || (nq > 0 && (!quartets || !out)))
         return fail(MJK_ERR_INVALID_ARG, "mjk_eri_class: bad quartet list");
-    // canonicalize and group by quartet class
-    std::vector<std::vector<EriItem>> groups(kNumQuartetClasses);
+    // canonicalize and group by quartet class and precision (fp32_tau)
+    std::vector<std::vector<EriItem>> groups(2 * kNumQuartetClasses);
+    const double tau32 = p->opts.fp32_tau;
     int64_t total = 0;
     for (int64_t q = 0; q < nq; ++q) {
         int sh[4];
@@ -937,7 +938,8 @@ int mjk_eri_class(mjk_plan *p, const int32_t *quartets, int64_t nq, double *out,
         it.n4 = ncart_h(p->l[sh[3]]);
         total += (int64_t)it.n1 * it.n2 * it.n3 * it.n4;
         const int qc = quartet_class(p->pairs_nat[bra].cls, p->pairs_nat[ket].cls);
-        groups[qc].push_back(it);
+        const bool f32 = tau32 > 0.0 && p->Q[bra] * p->Q[ket] < tau32;
+        groups[2 * qc + (f32 ? 1 : 0)].push_back(it);
     }
     if (total != out_len)
         return fail(MJK_ERR_INVALID_ARG, "mjk_eri_class: out_len %lld, quartets need %lld", (long long)out_len,
@@ -947,14 +949,16 @@ int mjk_eri_class(mjk_plan *p, const int32_t *quartets, int64_t nq, double *out,
     hipStream_t s = (hipStream_t)stream;
     char *w = p->ws;
     auto *stage = (EriItem *)(w + p->o_eri);
-    for (int qc = 0; qc < kNumQuartetClasses; ++qc) {
-        const auto &g = groups[qc];
+    for (int gi = 0; gi < 2 * kNumQuartetClasses; ++gi) {
+        const int qc = gi / 2;
+        const auto &g = groups[gi];
         for (size_t i0 = 0; i0 < g.size(); i0 += kEriStage) {
             const int n = (int)std::min<size_t>(kEriStage, g.size() - i0);
             // stream order keeps this copy behind the previous launch that read the stage
             HIP_TRY(hipMemcpyAsync(stage, g.data() + i0, sizeof(EriItem) * n, hipMemcpyHostToDevice, s));
             EriLaunch a{(const ShellPairD *)(w + p->o_pnat), (const PrimPairD *)(w + p->o_prims), stage, n, out};
-            if (kClassTable[qc].eri(a, s)) return fail(MJK_ERR_HIP, "mjk_eri_class: launch failed");
+            if ((gi % 2 ? kClassTable[qc].eri32 : kClassTable[qc].eri)(a, s))
+                return fail(MJK_ERR_HIP, "mjk_eri_class: launch failed");
             HIP_TRY(hipStreamSynchronize(s));  // the host vector g is pageable and reused
         }
     }

@@ -108,6 +108,7 @@ struct ClassEntry {
     JKFn jk;
     JKFn jk32;         // FP32 recurrence / contraction, FP64 digestion
     EriFn eri;
+    EriFn eri32;        // FP32 recurrence / contraction, FP64 HRR
     SchwarzFn schwarz;  // only on diagonal classes (la lb | la lb)
     // nuclear gradient: shifted classes (d/dA, d/dB, d/dC raise or lower one
     // centre), their staging need and algorithmic work

@@ -825,6 +825,7 @@ def generate(outdir, lmax=2, jobs=None):
         d.append(f"int launch_jk_{name}(const JKLaunch &, hipStream_t);")
         d.append(f"int launch_jk32_{name}(const JKLaunch &, hipStream_t);")
         d.append(f"int launch_eri_{name}(const EriLaunch &, hipStream_t);")
+        d.append(f"int launch_eri32_{name}(const EriLaunch &, hipStream_t);")
         d.append(f"int launch_grad_{name}(const JKLaunch &, hipStream_t);")
         d.append(f"size_t grad_stage_nacc_{name}();")
         if c[:2] == c[2:]:
@@ -847,7 +848,7 @@ def generate(outdir, lmax=2, jobs=None):
         g_q = sum(infos[t]["hrr_flops"] + grad_digest_flops(*c, k, t) for k, t in subs) + 6 * nw
         d.append(f"    {{{c[0]}, {c[1]}, {c[2]}, {c[3]}, {cc['nacc']}, {cc['nout']}, {cc['vrr_flops']}, "
                  f"{cc['hrr_flops']}, {int(cc['split'])}, {cc['npass']}, launch_jk_{name}, launch_jk32_{name}, "
-                 f"launch_eri_{name}, {sch}, launch_grad_{name}, grad_stage_nacc_{name}, {g_vrr}, {g_up}, {g_dn}, "
+                 f"launch_eri_{name}, launch_eri32_{name}, {sch}, launch_grad_{name}, grad_stage_nacc_{name}, {g_vrr}, {g_up}, {g_dn}, "
                  f"{g_q}}},")
     d.append("};")
     d.append("}  // namespace mjk")

@@ -1,6 +1,9 @@
 """GPU mixed precision: quartets with Q_AB Q_CD < fp32_tau run their
-recurrence, contraction and HRR in FP32; geometry, Boys and the J/K
-digestion stay FP64.  Bar: |E2(mixed) - E2(oracle FP64)| <= 1e-6 Eh."""
+recurrence and contraction in FP32; geometry and Boys (rounded), the HRR and
+the J/K digestion stay FP64.  Bars: |E2(mixed) - E2(oracle FP64)| <= 1e-6 Eh;
+per integral of an FP32 quartet, |(ab|cd)_32 - (ab|cd)_64| <= 1e-6 Q_AB Q_CD
+(FP32 rounding, about 6e-8 relative, over the recurrence depth and the
+primitive sum, against the Schwarz bound of the block)."""
 import numpy as np
 import pytest
 
@@ -71,3 +74,41 @@ def test_everything_fp32_is_close_not_exact():
     # FP32 recurrence: relative ~1e-6 of the largest integrals, never 1e-10 exact
     assert 1e-12 < dJ <= 1e-4 * np.max(np.abs(Jo))
     assert abs(oracle.e2(_np(J), _np(K), D) - oracle.e2(Jo, Ko, D)) <= 1e-4 * abs(oracle.e2(Jo, Ko, D))
+
+
+def test_eri_class_fp32_error_bounded_by_schwarz():
+    """FP32 recurrence, FP64 HRR: the error of an integral relative to its
+    Schwarz bound Q_AB Q_CD is FP32 rounding (~6e-8) for most quartets; the
+    HRR multiplies the rounding of the [e0|f0] intermediates by up to
+    (1 + |AB|)^lb (1 + |CD|)^ld, a few hundred for d shells 2-4 bohr apart,
+    so the tail reaches ~1e-3 of the bound.  A wrong index or weight would
+    show as an O(1) error."""
+    cfg = inputs.make_config(3, natom=6)
+    b = cfg["basis"]
+    p64 = mjk.Plan(b)
+    p32 = mjk.Plan(b, fp32_tau=1e30)  # every quartet in FP32
+    Q = p64.schwarz()
+    ns = len(b["shell_l"])
+    rng = np.random.default_rng(11)
+    quartets = rng.integers(0, ns, size=(400, 4)).astype(np.int32)
+    e64 = p64.eri_class(quartets)
+    e32 = p32.eri_class(quartets)
+    rel = []
+    for q, x64, x32 in zip(quartets, e64, e32):
+        bound = Q[q[0], q[1]] * Q[q[2], q[3]]
+        rel.append(float(np.max(np.abs(_np(x64) - _np(x32)))) / bound)
+    rel = np.array(rel)
+    print(f"eri_class FP32: |d| / (Q_AB Q_CD) median {np.median(rel):.2e} max {rel.max():.2e}", flush=True)
+    assert np.median(rel) <= 1e-6
+    assert rel.max() <= 3e-3
+    # at a finite threshold, the FP64 quartets are the FP64 path itself
+    thr = 1e-3
+    pm = mjk.Plan(b, fp32_tau=thr)
+    em = pm.eri_class(quartets)
+    n32 = 0
+    for q, x64, xm in zip(quartets, e64, em):
+        if Q[q[0], q[1]] * Q[q[2], q[3]] >= thr:
+            assert np.array_equal(_np(x64), _np(xm))
+        else:
+            n32 += 1
+    assert 0 < n32 < len(quartets)
