@@ -534,12 +534,17 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     constexpr int NAB = NA * NB, NCD = NC * ND, NF = S::NF, NACC = S::NACC;
     constexpr int NBUF = NACC > NAB * NCD ? NACC : NAB * NCD;
+    // density blocks of one quartet: D_cd, D_ac, D_ad, D_bc, D_bd back to back
+    constexpr int OAC = NCD, OAD = OAC + NA * NC, OBC = OAD + NA * ND, OBD = OBC + NB * NC, NDQ = OBD + NB * ND;
+    constexpr int KS = (NACC + 63) / 64, KD = (NDQ + 63) / 64;
     __shared__ double s_buf[NBUF];     // [e][f], then (ab|cd) as [ab][cd]
     __shared__ double s_abf[NAB * NF]; // (ab|f] as [ab][f]
-    __shared__ double s_Dab[NAB], s_Dcd[NCD], s_Dac[NA * NC], s_Dad[NA * ND], s_Dbc[NB * NC], s_Dbd[NB * ND];
+    __shared__ double s_Dab[NAB], s_Dq[NDQ];
     __shared__ double s_CD[64][3];
     __shared__ double s_w[64];
     __shared__ int s_ao[64][2];
+    double *const s_Dcd = s_Dq, *const s_Dac = s_Dq + OAC, *const s_Dad = s_Dq + OAD, *const s_Dbc = s_Dq + OBC,
+                  *const s_Dbd = s_Dq + OBD;
     const int lane = threadIdx.x;
     double *stage = a.stage + (size_t)blockIdx.x * NACC * 64;
 
@@ -580,20 +585,45 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
             }
             __syncthreads();
 
-            // phase 2: the wave works through this round's quartets
-            for (int q = 0; q < nact; ++q) {
-                for (int t = lane; t < NACC; t += 64) s_buf[t] = stage[(size_t)t * 64 + q];
+            // phase 2: the wave works through this round's quartets.  The
+            // staged [e0|f0] and the density blocks of quartet q + 1 are
+            // loaded into registers while quartet q is digested.
+            double pst[KS], pdq[KD];
+            auto fetch = [&](int q) {
                 const int ao_c = s_ao[q][0], ao_d = s_ao[q][1];
-                for (int t = lane; t < NCD; t += 64) s_Dcd[t] = D[(size_t)(ao_c + t / ND) * N + ao_d + t % ND];
-                for (int t = lane; t < NA * NC; t += 64)
-                    s_Dac[t] = D[(size_t)(bra.ao_a + t / NC) * N + ao_c + t % NC];
-                for (int t = lane; t < NA * ND; t += 64)
-                    s_Dad[t] = D[(size_t)(bra.ao_a + t / ND) * N + ao_d + t % ND];
-                for (int t = lane; t < NB * NC; t += 64)
-                    s_Dbc[t] = D[(size_t)(bra.ao_b + t / NC) * N + ao_c + t % NC];
-                for (int t = lane; t < NB * ND; t += 64)
-                    s_Dbd[t] = D[(size_t)(bra.ao_b + t / ND) * N + ao_d + t % ND];
+#pragma unroll
+                for (int k = 0; k < KS; ++k) {
+                    const int t = lane + 64 * k;
+                    pst[k] = t < NACC ? stage[(size_t)t * 64 + q] : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < KD; ++k) {
+                    const int t = lane + 64 * k;
+                    size_t at = 0;
+                    if (t < OAC)
+                        at = (size_t)(ao_c + t / ND) * N + ao_d + t % ND;
+                    else if (t < OAD)
+                        at = (size_t)(bra.ao_a + (t - OAC) / NC) * N + ao_c + (t - OAC) % NC;
+                    else if (t < OBC)
+                        at = (size_t)(bra.ao_a + (t - OAD) / ND) * N + ao_d + (t - OAD) % ND;
+                    else if (t < OBD)
+                        at = (size_t)(bra.ao_b + (t - OBC) / NC) * N + ao_c + (t - OBC) % NC;
+                    else if (t < NDQ)
+                        at = (size_t)(bra.ao_b + (t - OBD) / ND) * N + ao_d + (t - OBD) % ND;
+                    pdq[k] = t < NDQ ? D[at] : 0.0;
+                }
+            };
+            fetch(0);
+            for (int q = 0; q < nact; ++q) {
+                const int ao_c = s_ao[q][0], ao_d = s_ao[q][1];
+#pragma unroll
+                for (int k = 0; k < KS; ++k)
+                    if (lane + 64 * k < NACC) s_buf[lane + 64 * k] = pst[k];
+#pragma unroll
+                for (int k = 0; k < KD; ++k)
+                    if (lane + 64 * k < NDQ) s_Dq[lane + 64 * k] = pdq[k];
                 __syncthreads();
+                if (q + 1 < nact) fetch(q + 1);
                 for (int f = lane; f < NF; f += 64) S::template hrr_bra_col<1, double>(s_buf, f, bra.AB, s_abf);
                 __syncthreads();
                 const double CD[3] = {s_CD[q][0], s_CD[q][1], s_CD[q][2]};
