@@ -360,11 +360,15 @@ __global__ __launch_bounds__(64) void k_grad(JKLaunch a)
         const double *__restrict__ D = a.D + sg.mat_off;
         const int atA = sg.shell_atom[bra.A], atB = sg.shell_atom[bra.B];
         double bA[3] = {0.0, 0.0, 0.0}, bB[3] = {0.0, 0.0, 0.0};  // bra centres, summed over the item
+        int run = find_run(sg, b, kbeg);
+        const int run_end = sg.run_begin[b + 1];
 
         for (int k0 = kbeg; k0 < kend; k0 += 64) {
             const int nact = min(kend - k0, 64);
             const bool active = lane < nact;
-            const int ket_pos = sg.ket_begin + (active ? k0 + lane : k0);
+            const RoundKets rk = round_kets(sg, run, run_end, k0, lane);
+            const int pos0 = __builtin_amdgcn_readfirstlane(__shfl(rk.pos, 0, 64));
+            const int ket_pos = sg.ket_begin + (active ? rk.pos : pos0);
             const ShellPairD ket = sg.pairs[ket_pos];
             double s = 1.0;
             if (bra.same) s *= 2.0;

@@ -225,8 +225,70 @@ __device__ __forceinline__ void locate(const JKSeg &sg, int local, int &b, int &
             hi = mid;
     }
     b = lo;
-    kbeg = sg.ket_start[b] + (local - sg.chunk_prefix[b]) * sg.chunk;
-    kend = min(kbeg + sg.chunk, sg.ket_end[b]);
+    kbeg = (local - sg.chunk_prefix[b]) * sg.chunk;
+    kend = min(kbeg + sg.chunk, sg.ket_count[b]);
+}
+
+// the kept run of bra b that holds its ket number k (uniform)
+__device__ __forceinline__ int find_run(const JKSeg &sg, int b, int k)
+{
+    int lo = sg.run_begin[b], hi = sg.run_begin[b + 1];
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sg.runs[mid].start <= k)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Kets of one round: ket numbers k0 + lane of the current bra.  `r` is the
+// run holding k0 and `rend` one past the bra's last run (both uniform); r is
+// advanced to the run holding k0 + 64.  Lane j looks at the start of run
+// r + 1 + j; runs are never empty, so at most 63 of them start inside the
+// round and a 6-step search over those starts finds each lane's run.
+struct RoundKets {
+    int pos;    // bin position of the lane's ket (meaningless past the bra's last ket)
+    int last;   // last lane of the lane's run inside the round
+    bool head;  // the lane is the first of its run inside the round
+};
+
+__device__ __forceinline__ RoundKets round_kets(const JKSeg &sg, int &r, int rend, int k0, int lane)
+{
+    const KetRun cur = sg.runs[r];
+    const int rj = r + 1 + lane;
+    KetRun nx{0, 0};
+    if (rj < rend) nx = sg.runs[rj];
+    const int dj = rj < rend ? nx.start - k0 : (1 << 30);  // lane at which run r + 1 + j starts (>= 1)
+    int c = 0;  // runs after r that start at or before this lane
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+        const int t = __shfl(dj, c + step - 1, 64);
+        if (t <= lane) c += step;
+    }
+    const int src = c > 0 ? c - 1 : 0;
+    const int s1 = __shfl(nx.start, src, 64), p1 = __shfl(nx.pos, src, 64);
+    const int nxt = __shfl(dj, c, 64);
+    const int s = c > 0 ? s1 : cur.start, p = c > 0 ? p1 : cur.pos;
+    RoundKets o;
+    o.pos = p + (k0 + lane - s);
+    o.last = min(nxt - 1, 63);
+    o.head = lane == 0 || s == k0 + lane;
+    r += __popcll(__ballot(dj <= 64));
+    return o;
+}
+
+// sum of v over lanes [lane, last] (a segmented suffix sum; `last` is the
+// last lane of the lane's run, so at a run's head lane this is the run total)
+__device__ __forceinline__ double run_suffix_sum(double v, int lane, int last)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double o = __shfl_down(v, d, 64);
+        if (lane + d <= last) v += o;
+    }
+    return v;
 }
 
 // persistent blocks (one wave each) take items from the launch's counter;
@@ -259,7 +321,9 @@ __device__ __forceinline__ void stamp(const JKLaunch &a, int mol, int lane, bool
 //   Jt_ab += 2w D_cd   Jt_cd += 2w D_ab
 //   Kt_ac += w D_bd    Kt_ad += w D_bc    Kt_bc += w D_ad    Kt_bd += w D_ac
 // J = Jt + Jt^T and K = Kt + Kt^T afterwards (k_symmetrize).  Jt_ab is
-// bra-uniform, so it is reduced across the wave before its atomic.
+// bra-uniform, so it is reduced across the wave before its atomic; Kt_ac and
+// Kt_bc depend on the ket only through C, so they are summed over the lanes
+// of one run (same C) and added once per run.
 // ---------------------------------------------------------------------------
 template <int LA, int LB, int LC, int LD, typename T>
 __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
@@ -278,6 +342,8 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
     const double *__restrict__ D = a.D + sg.mat_off;
     double *__restrict__ Jm = a.J + sg.mat_off;
     double *__restrict__ Km = a.K + sg.mat_off;
+    int run = find_run(sg, b, kbeg);
+    const int run_end = sg.run_begin[b + 1];
 
     double Dab[NA * NB];
 #pragma unroll
@@ -289,9 +355,10 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
     for (int i = 0; i < NA * NB; ++i) jab[i] = 0.0;
 
     for (int k0 = kbeg; k0 < kend; k0 += 64) {
-        const int k = k0 + lane;
-        const bool active = k < kend;
-        const int ket_pos = sg.ket_begin + (active ? k : kbeg);
+        const bool active = k0 + lane < kend;
+        const RoundKets rk = round_kets(sg, run, run_end, k0, lane);
+        const int pos0 = __builtin_amdgcn_readfirstlane(__shfl(rk.pos, 0, 64));
+        const int ket_pos = sg.ket_begin + (active ? rk.pos : pos0);
         const ShellPairD ket = sg.pairs[ket_pos];
         T acc[C::NACC];
         contract_quartet<LA, LB, LC, LD, T>(bra, ket, sg.prims, active, acc);
@@ -326,6 +393,35 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
             for (int cd = 0; cd < NC * ND; ++cd) t += eri[ab * NC * ND + cd] * Dcd[cd];
             jab[ab] += 2.0 * w * t;
         }
+        // Kt_ac += w sum_{b,d} (ab|cd) D_bd and Kt_bc += w sum_{a,d} (ab|cd) D_ad,
+        // summed over the run before the atomic (all lanes take part)
+        const bool flush = active && rk.head;
+#pragma unroll
+        for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+                    for (int d = 0; d < ND; ++d)
+                        t += eri[((ia * NB + jb) * NC + c) * ND + d] * D[(size_t)(bra.ao_b + jb) * N + ket.ao_b + d];
+                t = run_suffix_sum(w * t, lane, rk.last);
+                if (flush) atomicAdd(Km + (size_t)(bra.ao_a + ia) * N + ket.ao_a + c, t);
+            }
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                    for (int d = 0; d < ND; ++d)
+                        t += eri[((ia * NB + jb) * NC + c) * ND + d] * D[(size_t)(bra.ao_a + ia) * N + ket.ao_b + d];
+                t = run_suffix_sum(w * t, lane, rk.last);
+                if (flush) atomicAdd(Km + (size_t)(bra.ao_b + jb) * N + ket.ao_a + c, t);
+            }
         if (active) {
 #pragma unroll
             for (int cd = 0; cd < NC * ND; ++cd) {
@@ -335,20 +431,9 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
                 const int c = cd / ND, d = cd % ND;
                 atomicAdd(Jm + (size_t)(ket.ao_a + c) * N + ket.ao_b + d, 2.0 * w * t);
             }
-            // Kt_ac += w sum_{b,d} (ab|cd) D_bd ; Kt_ad += w sum_{b,c} (ab|cd) D_bc
+            // Kt_ad += w sum_{b,c} (ab|cd) D_bc ; Kt_bd += w sum_{a,c} (ab|cd) D_ac
 #pragma unroll
-            for (int ia = 0; ia < NA; ++ia) {
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    double t = 0.0;
-#pragma unroll
-                    for (int jb = 0; jb < NB; ++jb)
-#pragma unroll
-                        for (int d = 0; d < ND; ++d)
-                            t += eri[((ia * NB + jb) * NC + c) * ND + d] *
-                                 D[(size_t)(bra.ao_b + jb) * N + ket.ao_b + d];
-                    atomicAdd(Km + (size_t)(bra.ao_a + ia) * N + ket.ao_a + c, w * t);
-                }
+            for (int ia = 0; ia < NA; ++ia)
 #pragma unroll
                 for (int d = 0; d < ND; ++d) {
                     double t = 0.0;
@@ -360,21 +445,8 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
                                  D[(size_t)(bra.ao_b + jb) * N + ket.ao_a + c];
                     atomicAdd(Km + (size_t)(bra.ao_a + ia) * N + ket.ao_b + d, w * t);
                 }
-            }
-            // Kt_bc += w sum_{a,d} (ab|cd) D_ad ; Kt_bd += w sum_{a,c} (ab|cd) D_ac
 #pragma unroll
-            for (int jb = 0; jb < NB; ++jb) {
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    double t = 0.0;
-#pragma unroll
-                    for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-                        for (int d = 0; d < ND; ++d)
-                            t += eri[((ia * NB + jb) * NC + c) * ND + d] *
-                                 D[(size_t)(bra.ao_a + ia) * N + ket.ao_b + d];
-                    atomicAdd(Km + (size_t)(bra.ao_b + jb) * N + ket.ao_a + c, w * t);
-                }
+            for (int jb = 0; jb < NB; ++jb)
 #pragma unroll
                 for (int d = 0; d < ND; ++d) {
                     double t = 0.0;
@@ -386,7 +458,6 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
                                  D[(size_t)(bra.ao_a + ia) * N + ket.ao_a + c];
                     atomicAdd(Km + (size_t)(bra.ao_b + jb) * N + ket.ao_b + d, w * t);
                 }
-            }
         }
     }
 #pragma unroll
@@ -537,6 +608,7 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
     // density blocks of one quartet: D_cd, D_ac, D_ad, D_bc, D_bd back to back
     constexpr int OAC = NCD, OAD = OAC + NA * NC, OBC = OAD + NA * ND, OBD = OBC + NB * NC, NDQ = OBD + NB * ND;
     constexpr int KS = (NACC + 63) / 64, KD = (NDQ + 63) / 64;
+    constexpr int KAC = (NA * NC + 63) / 64, KBC = (NB * NC + 63) / 64;
     __shared__ double s_buf[NBUF];     // [e][f], then (ab|cd) as [ab][cd]
     __shared__ double s_abf[NAB * NF]; // (ab|f] as [ab][f]
     __shared__ double s_Dab[NAB], s_Dq[NDQ];
@@ -563,12 +635,38 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
         double *__restrict__ Km = a.K + sg.mat_off;
         for (int t = lane; t < NAB; t += 64) s_Dab[t] = D[(size_t)(bra.ao_a + t / NB) * N + bra.ao_b + t % NB];
         double jab = 0.0;  // Jt_ab for ab = lane (lane < NAB), summed over the item
+        // Kt_ac and Kt_bc of the current C (element lane + 64 k), summed over
+        // consecutive quartets of one run and added when C changes
+        double kac[KAC], kbc[KBC];
+#pragma unroll
+        for (int k = 0; k < KAC; ++k) kac[k] = 0.0;
+#pragma unroll
+        for (int k = 0; k < KBC; ++k) kbc[k] = 0.0;
+        int cur_c = -1;
+        auto flush_c = [&]() {
+#pragma unroll
+            for (int k = 0; k < KAC; ++k) {
+                const int t = lane + 64 * k;
+                if (t < NA * NC) atomicAdd(Km + (size_t)(bra.ao_a + t / NC) * N + cur_c + t % NC, kac[k]);
+                kac[k] = 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < KBC; ++k) {
+                const int t = lane + 64 * k;
+                if (t < NB * NC) atomicAdd(Km + (size_t)(bra.ao_b + t / NC) * N + cur_c + t % NC, kbc[k]);
+                kbc[k] = 0.0;
+            }
+        };
+        int run = find_run(sg, b, kbeg);
+        const int run_end = sg.run_begin[b + 1];
 
         for (int k0 = kbeg; k0 < kend; k0 += 64) {
             // phase 1: one quartet per lane, passes into the staging slot
             const int nact = min(kend - k0, 64);
             const bool active = lane < nact;
-            const int ket_pos = sg.ket_begin + (active ? k0 + lane : k0);
+            const RoundKets rk = round_kets(sg, run, run_end, k0, lane);
+            const int pos0 = __builtin_amdgcn_readfirstlane(__shfl(rk.pos, 0, 64));
+            const int ket_pos = sg.ket_begin + (active ? rk.pos : pos0);
             const ShellPairD ket = sg.pairs[ket_pos];
             split_passes<LA, LB, LC, LD, 0, T>(bra, ket, sg.prims, active, stage, lane);
             {
@@ -616,6 +714,10 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
             fetch(0);
             for (int q = 0; q < nact; ++q) {
                 const int ao_c = s_ao[q][0], ao_d = s_ao[q][1];
+                if (ao_c != cur_c) {
+                    if (cur_c >= 0) flush_c();
+                    cur_c = ao_c;
+                }
 #pragma unroll
                 for (int k = 0; k < KS; ++k)
                     if (lane + 64 * k < NACC) s_buf[lane + 64 * k] = pst[k];
@@ -647,16 +749,20 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
                     for (int ab = 0; ab < NAB; ++ab) v += s_buf[ab * NCD + t] * s_Dab[ab];
                     atomicAdd(Jm + (size_t)(ao_c + t / ND) * N + ao_d + t % ND, 2.0 * w * v);
                 }
-                // Kt_ac += w sum_{b,d} (ab|cd) D_bd
-                for (int t = lane; t < NA * NC; t += 64) {
-                    const int ia = t / NC, c = t % NC;
-                    double v = 0.0;
+                // Kt_ac += w sum_{b,d} (ab|cd) D_bd (held until C changes)
 #pragma unroll
-                    for (int jb = 0; jb < NB; ++jb)
+                for (int k = 0; k < KAC; ++k) {
+                    const int t = lane + 64 * k;
+                    if (t < NA * NC) {
+                        const int ia = t / NC, c = t % NC;
+                        double v = 0.0;
 #pragma unroll
-                        for (int d = 0; d < ND; ++d)
-                            v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dbd[jb * ND + d];
-                    atomicAdd(Km + (size_t)(bra.ao_a + ia) * N + ao_c + c, w * v);
+                        for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+                            for (int d = 0; d < ND; ++d)
+                                v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dbd[jb * ND + d];
+                        kac[k] += w * v;
+                    }
                 }
                 // Kt_ad += w sum_{b,c} (ab|cd) D_bc
                 for (int t = lane; t < NA * ND; t += 64) {
@@ -669,16 +775,20 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
                             v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dbc[jb * NC + c];
                     atomicAdd(Km + (size_t)(bra.ao_a + ia) * N + ao_d + d, w * v);
                 }
-                // Kt_bc += w sum_{a,d} (ab|cd) D_ad
-                for (int t = lane; t < NB * NC; t += 64) {
-                    const int jb = t / NC, c = t % NC;
-                    double v = 0.0;
+                // Kt_bc += w sum_{a,d} (ab|cd) D_ad (held until C changes)
 #pragma unroll
-                    for (int ia = 0; ia < NA; ++ia)
+                for (int k = 0; k < KBC; ++k) {
+                    const int t = lane + 64 * k;
+                    if (t < NB * NC) {
+                        const int jb = t / NC, c = t % NC;
+                        double v = 0.0;
 #pragma unroll
-                        for (int d = 0; d < ND; ++d)
-                            v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dad[ia * ND + d];
-                    atomicAdd(Km + (size_t)(bra.ao_b + jb) * N + ao_c + c, w * v);
+                        for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                            for (int d = 0; d < ND; ++d)
+                                v += s_buf[(ia * NB + jb) * NCD + c * ND + d] * s_Dad[ia * ND + d];
+                        kbc[k] += w * v;
+                    }
                 }
                 // Kt_bd += w sum_{a,c} (ab|cd) D_ac
                 for (int t = lane; t < NB * ND; t += 64) {
@@ -694,6 +804,7 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
                 __syncthreads();
             }
         }
+        if (cur_c >= 0) flush_c();
         if (lane < NAB) atomicAdd(Jm + (size_t)(bra.ao_a + lane / NB) * N + bra.ao_b + lane % NB, jab);
         stamp(a, sg.mol, lane, true);
         __syncthreads();

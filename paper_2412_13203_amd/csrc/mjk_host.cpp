@@ -88,6 +88,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Bin {
     int cls, kb;
     int begin, count;  // positions in the sorted pair order
+    int nrun;          // distinct first shells (runs) among its pairs
 };
 
 struct BinPair {
@@ -100,7 +101,7 @@ struct WorkList {
     int bp;            // bin pair
     int fp32;          // 1: FP32 recurrence (Q_AB Q_CD < fp32_tau)
     size_t off;        // int offset in the work-list region:
-                       //   ket_start[nbra], ket_end[nbra], chunk_prefix[nbra + 1]
+                       //   ket_count[nbra], run_begin[nbra + 1], chunk_prefix[nbra + 1]
     int nbra;
     int chunk;         // kets per item
     int nitems;
@@ -158,8 +159,9 @@ struct mjk_plan {
     int qpl[kNumQuartetClasses];         // quartets per lane, per class
     std::vector<Group> groups;
     // workspace layout (byte offsets)
-    size_t o_xyz, o_atom, o_poff, o_np, o_exps, o_coefs, o_pnat, o_psort, o_prims, o_Q, o_cls, o_work, o_segs,
-        o_queue, o_eri, o_stage, total;
+    size_t o_xyz, o_atom, o_poff, o_np, o_exps, o_coefs, o_pnat, o_psort, o_prims, o_Q, o_cls, o_work, o_runs,
+        o_segs, o_queue, o_eri, o_stage, total;
+    size_t max_runs = 0;      // kept-run records: bound over all screening outcomes
     int nslot = 0;            // staging slots for split classes
     size_t stage_nacc = 0;    // largest split-class accumulator count present (J/K and gradient)
     int64_t max_items = 0;    // upper bound of the items of one segment (one quartet per lane)
@@ -210,10 +212,10 @@ void rechunk(mjk_plan *p, int qcls)
         const int qc = p->bps[wl.bp].qcls;
         if (qcls >= 0 && qc != qcls) continue;
         wl.chunk = kChunk * p->qpl[qc];
-        const int32_t *st = p->work.data() + wl.off, *en = st + wl.nbra;
-        int32_t *pre = p->work.data() + wl.off + 2 * (size_t)wl.nbra;
+        const int32_t *cnt = p->work.data() + wl.off;
+        int32_t *pre = p->work.data() + wl.off + 2 * (size_t)wl.nbra + 1;
         pre[0] = 0;
-        for (int b = 0; b < wl.nbra; ++b) pre[b + 1] = pre[b] + (en[b] - st[b] + wl.chunk - 1) / wl.chunk;
+        for (int b = 0; b < wl.nbra; ++b) pre[b + 1] = pre[b] + (cnt[b] + wl.chunk - 1) / wl.chunk;
         wl.nitems = pre[wl.nbra];
     }
 }
@@ -227,9 +229,10 @@ JKSeg make_seg(const mjk_plan *p, const WorkList &wl, int64_t mat_off, int mol)
     JKSeg g{};
     g.pairs = (const ShellPairD *)(w + p->o_psort);
     g.prims = (const PrimPairD *)(w + p->o_prims);
-    g.ket_start = wk;
-    g.ket_end = wk + X.count;
-    g.chunk_prefix = wk + 2 * X.count;
+    g.runs = (const KetRun *)(w + p->o_runs);
+    g.ket_count = wk;
+    g.run_begin = wk + X.count;
+    g.chunk_prefix = wk + 2 * X.count + 1;
     g.shell_atom = (const int32_t *)(w + p->o_atom);
     g.mat_off = mat_off;
     g.nbf = p->nbf;
@@ -544,15 +547,25 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
         return fail(MJK_ERR_UNSUPPORTED, "mjk_plan_create: %lld primitive pairs exceed int32", (long long)pp);
     }
 
-    // bins by (class, K-bucket): sizes known now, Q order decided at bind
+    // bins by (class, K-bucket): sizes and runs (distinct first shells) known
+    // now, the order inside a run (Q) decided at bind
     std::vector<int> bin_size(kNumPairClasses * kNumKBuckets, 0);
-    for (const auto &sp : p->pairs_nat) bin_size[sp.cls * kNumKBuckets + kbucket(sp.nprim)]++;
+    std::vector<std::vector<int32_t>> bin_first(kNumPairClasses * kNumKBuckets);
+    for (const auto &sp : p->pairs_nat) {
+        const int key = sp.cls * kNumKBuckets + kbucket(sp.nprim);
+        bin_size[key]++;
+        bin_first[key].push_back(sp.A);
+    }
     int pos = 0;
     for (int c = 0; c < kNumPairClasses; ++c)
         for (int kb = 0; kb < kNumKBuckets; ++kb) {
-            const int n = bin_size[c * kNumKBuckets + kb];
+            const int key = c * kNumKBuckets + kb;
+            const int n = bin_size[key];
             if (n == 0) continue;
-            p->bins.push_back({c, kb, pos, n});
+            auto &f = bin_first[key];
+            std::sort(f.begin(), f.end());
+            const int nrun = (int)(std::unique(f.begin(), f.end()) - f.begin());
+            p->bins.push_back({c, kb, pos, n, nrun});
             pos += n;
         }
     // bin pairs X >= Y (bin order = (class, bucket) order, so class(X) >= class(Y))
@@ -570,12 +583,20 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
                 wl.off = woff;
                 wl.nbra = p->bins[X].count;
                 wl.chunk = kChunk;
-                woff += 3 * (size_t)p->bins[X].count + 1;
+                woff += 3 * (size_t)p->bins[X].count + 2;
                 p->lists.push_back(wl);
+                // a bra keeps at most one record per run of the ket bin; FP32
+                // lists stay empty without an FP32 threshold
+                if (prec == 0 || o.fp32_tau > 0.0) p->max_runs += (size_t)p->bins[X].count * p->bins[Y].nrun;
             }
             p->bps.push_back(bp);
         }
     p->work_ints = woff;
+    if (p->max_runs > (size_t)INT32_MAX) {
+        const size_t nr = p->max_runs;
+        delete p;
+        return fail(MJK_ERR_UNSUPPORTED, "mjk_plan_create: %zu kept-run records exceed int32", nr);
+    }
     // split classes present: staging for one item per persistent block;
     // a launch never has more blocks than work items
     for (const auto &bp : p->bps) {
@@ -610,6 +631,7 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
     p->o_Q = take(sizeof(double) * p->npair);
     p->o_cls = take(sizeof(int32_t) * p->npair);
     p->o_work = take(sizeof(int32_t) * p->work_ints);
+    p->o_runs = take(sizeof(KetRun) * std::max<size_t>(p->max_runs, 1));
     p->o_segs = take(in_batch ? 0 : sizeof(JKSeg) * p->lists.size());
     p->o_queue = take(in_batch ? 0 : sizeof(uint32_t) * 2 * kNumQuartetClasses);
     p->o_eri = take(sizeof(EriItem) * kEriStage);
@@ -680,63 +702,105 @@ static int plan_bind(mjk_plan *p, void *workspace, size_t bytes, hipStream_t s)
         p->pairs_nat[k].Q = p->Q[k];
     }
 
-    // sort into bins: (class, K-bucket) ascending, Q descending, index ascending
+    // sort into bins: (class, K-bucket) ascending, then by first shell (runs),
+    // inside a run Q descending, index ascending
     p->sorted.resize(p->npair);
     for (int k = 0; k < p->npair; ++k) p->sorted[k] = k;
     std::stable_sort(p->sorted.begin(), p->sorted.end(), [&](int x, int y) {
         const ShellPairD &a = p->pairs_nat[x], &b = p->pairs_nat[y];
         const int ka = a.cls * kNumKBuckets + kbucket(a.nprim), kb = b.cls * kNumKBuckets + kbucket(b.nprim);
         if (ka != kb) return ka < kb;
+        if (a.A != b.A) return a.A < b.A;
         if (a.Q != b.Q) return a.Q > b.Q;
         return x < y;
     });
     std::vector<ShellPairD> psort(p->npair);
     for (int k = 0; k < p->npair; ++k) psort[k] = p->pairs_nat[p->sorted[k]];
     HIP_TRY(hipMemcpyAsync(w + p->o_psort, psort.data(), sizeof(ShellPairD) * p->npair, hipMemcpyHostToDevice, s));
+    // runs of every bin: bin-relative start and length
+    std::vector<std::vector<std::pair<int, int>>> bin_runs(p->bins.size());
+    for (size_t y = 0; y < p->bins.size(); ++y) {
+        const Bin &Y = p->bins[y];
+        auto &rs = bin_runs[y];
+        for (int k = 0; k < Y.count; ++k) {
+            if (k == 0 || psort[Y.begin + k].A != psort[Y.begin + k - 1].A)
+                rs.push_back({k, 1});
+            else
+                rs.back().second++;
+        }
+        if ((int)rs.size() != Y.nrun) return fail(MJK_ERR_STATE, "mjk_plan_bind: bin %zu: run count changed since create", y);
+    }
 
-    // stage 2: per bin pair, per bra, the kept ket prefix of the ket bin
-    // (Q_AB Q_CD >= schwarz_tau), split into its FP64 prefix
-    // (Q_AB Q_CD >= fp32_tau) and FP32 remainder
+    // stage 2: per bin pair, per bra, the kept prefix of every run of the ket
+    // bin (Q_AB Q_CD >= schwarz_tau; with coinciding bins also ket <= bra),
+    // split into its FP64 part (Q_AB Q_CD >= fp32_tau) and FP32 remainder
     const double tau = p->opts.schwarz_tau, tau32 = p->opts.fp32_tau;
     p->work.assign(p->work_ints, 0);
+    std::vector<KetRun> runs;
+    runs.reserve(p->max_runs);
     int64_t nq_kept = 0, nprimq = 0, ncart = 0, nq32 = 0;
     double flops = 0.0, gflops = 0.0;
-    auto prefix_len = [&](const Bin &Y, double qb, double thr) {
-        int lo = 0, hi = Y.count;  // first k with qb * Q_k < thr
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (qb * psort[Y.begin + mid].Q < thr)
-                hi = mid;
+    // kets of [lo, lo + n) (bin positions of Y, Q descending) with qb * Q >= thr
+    auto kept_len = [&](const Bin &Y, int lo, int n, double qb, double thr) {
+        int a0 = 0, a1 = n;
+        while (a0 < a1) {
+            const int mid = (a0 + a1) >> 1;
+            if (qb * psort[Y.begin + lo + mid].Q < thr)
+                a1 = mid;
             else
-                lo = mid + 1;
+                a0 = mid + 1;
         }
-        return lo;
+        return a0;
     };
+    std::vector<KetRun> r32;
     for (size_t il = 0; il < p->lists.size(); il += 2) {
         WorkList &l64 = p->lists[il], &l32 = p->lists[il + 1];
         const BinPair &bp = p->bps[l64.bp];
         const Bin &X = p->bins[bp.X], &Y = p->bins[bp.Y];
+        const auto &yr = bin_runs[bp.Y];
         const ClassEntry &ce = kClassTable[bp.qcls];
-        int32_t *s64 = p->work.data() + l64.off, *e64 = s64 + X.count;
-        int32_t *s32 = p->work.data() + l32.off, *e32 = s32 + X.count;
+        int32_t *c64 = p->work.data() + l64.off, *rb64 = c64 + X.count;
+        int32_t *c32 = p->work.data() + l32.off, *rb32 = c32 + X.count;
         std::vector<int64_t> ynp(Y.count + 1, 0);  // prefix of K_C K_D over the ket bin
         for (int k = 0; k < Y.count; ++k) ynp[k + 1] = ynp[k] + psort[Y.begin + k].nprim;
+        r32.clear();
         int64_t q64 = 0, q32 = 0, pq64 = 0, pq32 = 0;
         for (int b = 0; b < X.count; ++b) {
             const double qb = psort[X.begin + b].Q;
-            int keep = prefix_len(Y, qb, tau);
-            if (bp.X == bp.Y) keep = std::min(keep, b + 1);
-            int c64 = tau32 > 0.0 ? std::min(keep, prefix_len(Y, qb, tau32)) : keep;
-            s64[b] = 0;
-            e64[b] = c64;
-            s32[b] = c64;
-            e32[b] = keep;
             const int64_t nb = psort[X.begin + b].nprim;
-            q64 += c64;
-            q32 += keep - c64;
-            pq64 += nb * ynp[c64];
-            pq32 += nb * (ynp[keep] - ynp[c64]);
+            rb64[b] = (int32_t)runs.size();
+            rb32[b] = (int32_t)r32.size();
+            int n64 = 0, n32 = 0;
+            for (const auto &run : yr) {
+                int len = run.second;
+                if (bp.X == bp.Y) {
+                    if (run.first > b) break;
+                    len = std::min(len, b - run.first + 1);
+                }
+                const int keep = kept_len(Y, run.first, len, qb, tau);
+                const int k64 = tau32 > 0.0 ? std::min(keep, kept_len(Y, run.first, keep, qb, tau32)) : keep;
+                if (k64 > 0) {
+                    runs.push_back({n64, run.first});
+                    n64 += k64;
+                    pq64 += nb * (ynp[run.first + k64] - ynp[run.first]);
+                }
+                if (keep > k64) {
+                    r32.push_back({n32, run.first + k64});
+                    n32 += keep - k64;
+                    pq32 += nb * (ynp[run.first + keep] - ynp[run.first + k64]);
+                }
+            }
+            c64[b] = n64;
+            c32[b] = n32;
+            q64 += n64;
+            q32 += n32;
         }
+        rb64[X.count] = (int32_t)runs.size();
+        rb32[X.count] = (int32_t)r32.size();
+        const int32_t base32 = (int32_t)runs.size();
+        for (int b = 0; b <= X.count; ++b) rb32[b] += base32;
+        runs.insert(runs.end(), r32.begin(), r32.end());
+        if (runs.size() > p->max_runs) return fail(MJK_ERR_STATE, "mjk_plan_bind: kept-run records exceed their bound");
         const int nout = ncart_h(ce.la) * ncart_h(ce.lb) * ncart_h(ce.lc) * ncart_h(ce.ld);
         const int L = ce.la + ce.lb + ce.lc + ce.ld;
         const double fpq = ce.vrr_flops + prim_overhead_flops(L), fq = ce.hrr_flops + 12.0 * nout;
@@ -757,8 +821,10 @@ static int plan_bind(mjk_plan *p, void *workspace, size_t bytes, hipStream_t s)
         flops += l64.cost + l32.cost;
         gflops += l64.gcost + l32.gcost;
     }
+    if (!runs.empty())
+        HIP_TRY(hipMemcpyAsync(w + p->o_runs, runs.data(), sizeof(KetRun) * runs.size(), hipMemcpyHostToDevice, s));
     rechunk(p, -1);
-    if (int rc = upload_work(p, s)) return rc;  // synchronizes: psort is released on return
+    if (int rc = upload_work(p, s)) return rc;  // synchronizes: psort and runs are released on return
     p->stats.nquartet_kept = nq_kept;
     p->stats.nquartet_fp32 = nq32;
     p->stats.nprim_quartet_kept = nprimq;

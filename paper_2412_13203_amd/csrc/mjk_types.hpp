@@ -43,14 +43,26 @@ struct alignas(16) EriItem {
     int32_t n1, n2, n3, n4;// caller's component counts (A, B, C, D)
 };
 
+// One kept run of a bra's ket list.  Inside a bin the pairs are ordered by
+// their first shell C, then by Schwarz factor (descending); a run is the
+// pairs of one C.  A bra keeps a prefix of every run (screening and, when the
+// bra and ket bins coincide, the ket <= bra triangle both cut prefixes), so
+// its kets, numbered 0, 1, ... in run order, are described by the runs it
+// keeps: run r holds kets [start_r, start_{r+1}) beginning at bin position pos_r.
+struct KetRun {
+    int32_t start;               // first ket number of the run (per bra, per precision)
+    int32_t pos;                 // bin position of that ket
+};
+
 // One segment of a class launch: the quartets of one (bra bin, ket bin) pair
 // of one molecule at one precision.  Work items of a launch are numbered
 // across its segments (item_begin); an item is one bra pair x `chunk` kets.
 struct alignas(16) JKSeg {
     const ShellPairD *pairs;     // the molecule's class-sorted pair table
     const PrimPairD *prims;
-    const int32_t *ket_start;    // per bra: first ket (bin position)
-    const int32_t *ket_end;      // per bra: one past the last ket
+    const KetRun *runs;          // the molecule's kept-run table
+    const int32_t *ket_count;    // per bra: kept kets
+    const int32_t *run_begin;    // per bra: first kept run (nbra + 1, into runs)
     const int32_t *chunk_prefix; // per bra: exclusive prefix of chunks (nbra + 1)
     const int32_t *shell_atom;   // gradient: atom of each shell
     int64_t mat_off;             // first element of this molecule's D, J, K
