@@ -153,7 +153,7 @@ struct QuartetAO {
     int a, b, c, d;  // first AO of each shell
 };
 
-__device__ __forceinline__ double wdens(const double *__restrict__ D, int N, const QuartetAO &o, int ia, int jb,
+__device__ __forceinline__ double wdens(gptr<double> __restrict__ D, int N, const QuartetAO &o, int ia, int jb,
                                         int kc, int ld)
 {
     const double dab = D[(size_t)(o.a + ia) * N + o.b + jb], dcd = D[(size_t)(o.c + kc) * N + o.d + ld];
@@ -172,7 +172,7 @@ constexpr int kGradWRegMax = 36;
 template <int LA, int LB, int LC, int LD, int S>
 __device__ __forceinline__ void grad_sub_lane(const ShellPairD &bra, const ShellPairD &ket,
                                               const PrimPairD *__restrict__ prims, bool active,
-                                              const double *__restrict__ D, int N, const QuartetAO &o,
+                                              gptr<double> __restrict__ D, int N, const QuartetAO &o,
                                               const double *Wr, double g[3])
 {
     using G = GradSub<LA, LB, LC, LD, S>;
@@ -225,7 +225,7 @@ __device__ __forceinline__ void grad_sub_lane(const ShellPairD &bra, const Shell
 template <int LA, int LB, int LC, int LD, int S>
 __device__ __forceinline__ void grad_sub_lane_if(const ShellPairD &bra, const ShellPairD &ket,
                                                  const PrimPairD *__restrict__ prims, bool active,
-                                                 const double *__restrict__ D, int N, const QuartetAO &o,
+                                                 gptr<double> __restrict__ D, int N, const QuartetAO &o,
                                                  const double *Wr, double gA[3], double gB[3], double gC[3])
 {
     using G = GradSub<LA, LB, LC, LD, S>;
@@ -247,7 +247,7 @@ constexpr bool grad_sub_lane_used()
 template <int LA, int LB, int LC, int LD, int S>
 __device__ __forceinline__ void grad_sub_split_run(const ShellPairD &bra, const ShellPairD &ket,
                                                    const PrimPairD *__restrict__ prims, bool active,
-                                                   const double *__restrict__ D, int N, int nact, int lane,
+                                                   gptr<double> __restrict__ D, int N, int nact, int lane,
                                                    double *__restrict__ stage, double *__restrict__ s_abf,
                                                    double *__restrict__ s_W, const double *s_w, const double (*s_CD)[3],
                                                    const int (*s_ao)[2], double gA[3], double gB[3], double gC[3])
@@ -351,17 +351,17 @@ __global__ __launch_bounds__(64) void k_grad(JKLaunch a)
     __syncthreads();
 
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
-        const JKSeg sg = a.segs[find_seg(a, item)];
+        const JKSeg sg = ldg(a.segs + find_seg(a, item));
         int b, kbeg, kend;
         locate(sg, item - sg.item_begin, b, kbeg, kend);
         const int bra_pos = sg.bra_begin + b;
-        const ShellPairD bra = sg.pairs[bra_pos];
+        const ShellPairD bra = ldg(sg.pairs + bra_pos);
         const int N = sg.nbf;
-        const double *__restrict__ D = a.D + sg.mat_off;
-        const int atA = sg.shell_atom[bra.A], atB = sg.shell_atom[bra.B];
+        const gptr<double> __restrict__ D = gview(a.D + sg.mat_off);
+        const int atA = ldg(sg.shell_atom + bra.A), atB = ldg(sg.shell_atom + bra.B);
         double bA[3] = {0.0, 0.0, 0.0}, bB[3] = {0.0, 0.0, 0.0};  // bra centres, summed over the item
         int run = find_run(sg, b, kbeg);
-        const int run_end = sg.run_begin[b + 1];
+        const int run_end = ldg(sg.run_begin + b + 1);
 
         for (int k0 = kbeg; k0 < kend; k0 += 64) {
             const int nact = min(kend - k0, 64);
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(64) void k_grad(JKLaunch a)
             const RoundKets rk = round_kets(sg, run, run_end, k0, lane);
             const int pos0 = __builtin_amdgcn_readfirstlane(__shfl(rk.pos, 0, 64));
             const int ket_pos = sg.ket_begin + (active ? rk.pos : pos0);
-            const ShellPairD ket = sg.pairs[ket_pos];
+            const ShellPairD ket = ldg(sg.pairs + ket_pos);
             double s = 1.0;
             if (bra.same) s *= 2.0;
             if (ket.same) s *= 2.0;
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(64) void k_grad(JKLaunch a)
                                                       s_W, s_w, s_CD, s_ao, gA, gB, gC);
             }
             if (active) {
-                const int atC = sg.shell_atom[ket.A], atD = sg.shell_atom[ket.B];
+                const int atC = ldg(sg.shell_atom + ket.A), atD = ldg(sg.shell_atom + ket.B);
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     atomicAdd(&s_g[3 * atC + i], gC[i]);

@@ -35,6 +35,30 @@ namespace mjk {
 
 __host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 
+// The tables the kernels read (pairs, primitive pairs, work lists, segments,
+// D) are not written while a kernel runs.  Loads through these constant
+// (address space 4) views become scalar loads where the address is uniform
+// and global loads elsewhere, instead of generic flat loads, which also tie
+// up the LDS/scalar counters.  Never used for memory a kernel writes.
+template <typename T>
+using gptr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> gview(const T *p)
+{
+    return (gptr<T>)p;
+}
+
+template <typename T>
+__device__ __forceinline__ T ldg(const T *p)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *gview(p);
+#else
+    return *p;  // the host pass only parses device code
+#endif
+}
+
 // ---------------------------------------------------------------------------
 // Boys function F_m(T), m = 0..L (Section 2.2's analytic [00|00] needs it).
 // T < TMAX: Taylor expansion of F_L and exp(-T) about the nearest grid point
@@ -109,7 +133,7 @@ __device__ __forceinline__ double prim_geom(const PrimPairD &b, const PrimPairD 
 
 __device__ __forceinline__ PrimPairD load_prim(const PrimPairD *__restrict__ p)
 {
-    return *p;
+    return ldg(p);
 }
 
 
@@ -206,7 +230,7 @@ __device__ __forceinline__ int find_seg(const JKLaunch &a, int item)
     int lo = 0, hi = a.nseg;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (a.segs[mid].item_begin <= item)
+        if (ldg(&a.segs[mid].item_begin) <= item)
             lo = mid;
         else
             hi = mid;
@@ -219,23 +243,23 @@ __device__ __forceinline__ void locate(const JKSeg &sg, int local, int &b, int &
     int lo = 0, hi = sg.nbra;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (sg.chunk_prefix[mid] <= local)
+        if (ldg(sg.chunk_prefix + mid) <= local)
             lo = mid;
         else
             hi = mid;
     }
     b = lo;
-    kbeg = (local - sg.chunk_prefix[b]) * sg.chunk;
-    kend = min(kbeg + sg.chunk, sg.ket_count[b]);
+    kbeg = (local - ldg(sg.chunk_prefix + b)) * sg.chunk;
+    kend = min(kbeg + sg.chunk, ldg(sg.ket_count + b));
 }
 
 // the kept run of bra b that holds its ket number k (uniform)
 __device__ __forceinline__ int find_run(const JKSeg &sg, int b, int k)
 {
-    int lo = sg.run_begin[b], hi = sg.run_begin[b + 1];
+    int lo = ldg(sg.run_begin + b), hi = ldg(sg.run_begin + b + 1);
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (sg.runs[mid].start <= k)
+        if (ldg(&sg.runs[mid].start) <= k)
             lo = mid;
         else
             hi = mid;
@@ -256,10 +280,10 @@ struct RoundKets {
 
 __device__ __forceinline__ RoundKets round_kets(const JKSeg &sg, int &r, int rend, int k0, int lane)
 {
-    const KetRun cur = sg.runs[r];
+    const KetRun cur = ldg(sg.runs + r);
     const int rj = r + 1 + lane;
     KetRun nx{0, 0};
-    if (rj < rend) nx = sg.runs[rj];
+    if (rj < rend) nx = ldg(sg.runs + rj);
     const int dj = rj < rend ? nx.start - k0 : (1 << 30);  // lane at which run r + 1 + j starts (>= 1)
     int c = 0;  // runs after r that start at or before this lane
 #pragma unroll
@@ -332,18 +356,18 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     const int item = blockIdx.x;
     const int lane = threadIdx.x;
-    const JKSeg sg = a.segs[find_seg(a, item)];
+    const JKSeg sg = ldg(a.segs + find_seg(a, item));
     int b, kbeg, kend;
     locate(sg, item - sg.item_begin, b, kbeg, kend);
     stamp(a, sg.mol, lane, false);
     const int bra_pos = sg.bra_begin + b;
-    const ShellPairD bra = sg.pairs[bra_pos];
+    const ShellPairD bra = ldg(sg.pairs + bra_pos);
     const int N = sg.nbf;
-    const double *__restrict__ D = a.D + sg.mat_off;
+    const gptr<double> __restrict__ D = gview(a.D + sg.mat_off);
     double *__restrict__ Jm = a.J + sg.mat_off;
     double *__restrict__ Km = a.K + sg.mat_off;
     int run = find_run(sg, b, kbeg);
-    const int run_end = sg.run_begin[b + 1];
+    const int run_end = ldg(sg.run_begin + b + 1);
 
     double Dab[NA * NB];
 #pragma unroll
@@ -359,7 +383,7 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
         const RoundKets rk = round_kets(sg, run, run_end, k0, lane);
         const int pos0 = __builtin_amdgcn_readfirstlane(__shfl(rk.pos, 0, 64));
         const int ket_pos = sg.ket_begin + (active ? rk.pos : pos0);
-        const ShellPairD ket = sg.pairs[ket_pos];
+        const ShellPairD ket = ldg(sg.pairs + ket_pos);
         T acc[C::NACC];
         contract_quartet<LA, LB, LC, LD, T>(bra, ket, sg.prims, active, acc);
         double eri[C::NOUT];
@@ -623,14 +647,14 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
     for (;;) {
         const int item = next_item(a, lane);
         if (item >= a.nitems) break;
-        const JKSeg sg = a.segs[find_seg(a, item)];
+        const JKSeg sg = ldg(a.segs + find_seg(a, item));
         int b, kbeg, kend;
         locate(sg, item - sg.item_begin, b, kbeg, kend);
         stamp(a, sg.mol, lane, false);
         const int bra_pos = sg.bra_begin + b;
-        const ShellPairD bra = sg.pairs[bra_pos];
+        const ShellPairD bra = ldg(sg.pairs + bra_pos);
         const int N = sg.nbf;
-        const double *__restrict__ D = a.D + sg.mat_off;
+        const gptr<double> __restrict__ D = gview(a.D + sg.mat_off);
         double *__restrict__ Jm = a.J + sg.mat_off;
         double *__restrict__ Km = a.K + sg.mat_off;
         for (int t = lane; t < NAB; t += 64) s_Dab[t] = D[(size_t)(bra.ao_a + t / NB) * N + bra.ao_b + t % NB];
@@ -658,7 +682,7 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
             }
         };
         int run = find_run(sg, b, kbeg);
-        const int run_end = sg.run_begin[b + 1];
+        const int run_end = ldg(sg.run_begin + b + 1);
 
         for (int k0 = kbeg; k0 < kend; k0 += 64) {
             // phase 1: one quartet per lane, passes into the staging slot
@@ -667,7 +691,7 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
             const RoundKets rk = round_kets(sg, run, run_end, k0, lane);
             const int pos0 = __builtin_amdgcn_readfirstlane(__shfl(rk.pos, 0, 64));
             const int ket_pos = sg.ket_begin + (active ? rk.pos : pos0);
-            const ShellPairD ket = sg.pairs[ket_pos];
+            const ShellPairD ket = ldg(sg.pairs + ket_pos);
             split_passes<LA, LB, LC, LD, 0, T>(bra, ket, sg.prims, active, stage, lane);
             {
                 double s = 1.0;
