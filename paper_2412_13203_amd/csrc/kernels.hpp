@@ -350,7 +350,7 @@ __device__ __forceinline__ void stamp(const JKLaunch &a, int mol, int lane, bool
 // of one run (same C) and added once per run.
 // ---------------------------------------------------------------------------
 template <int LA, int LB, int LC, int LD, typename T>
-__global__ __launch_bounds__(64) void k_jk(JKLaunch a)
+__device__ __forceinline__ void jk_lane_body(const JKLaunch &a)
 {
     using C = EriClass<LA, LB, LC, LD>;
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
@@ -490,6 +490,34 @@ __global__ __launch_bounds__(64) void k_jk(JKLaunch a)
         if (lane == 0) atomicAdd(Jm + (size_t)(bra.ao_a + ab / NB) * N + bra.ao_b + ab % NB, t);
     }
     stamp(a, sg.mol, lane, true);
+}
+
+// Resident waves per SIMD asked of the compiler for a few per-lane classes
+// whose register count sits just above an occupancy step (0: no request).
+// Measured per class: (dp|ps) 264 VGPRs -> 256, 1 -> 2 waves, 7.4 -> 5.7 ms;
+// (ds|pp) 280 -> 256, 5.6 -> 5.1 ms; (ps|ps) 130 -> 128, 2.31 -> 2.20 ms;
+// (pp|ps) 191 -> 168, 1.89 -> 1.79 ms.  The same request slowed (ds|ps) and
+// (pp|ss), whose reduced budgets spill.
+template <int LA, int LB, int LC, int LD>
+constexpr int jk_waves()
+{
+    return (LA == 2 && LB == 1 && LC == 1 && LD == 0)   ? 2
+           : (LA == 2 && LB == 0 && LC == 1 && LD == 1) ? 2
+           : (LA == 1 && LB == 0 && LC == 1 && LD == 0) ? 4
+           : (LA == 1 && LB == 1 && LC == 1 && LD == 0) ? 3
+                                                        : 0;
+}
+
+template <int LA, int LB, int LC, int LD, typename T>
+__global__ __launch_bounds__(64) void k_jk(JKLaunch a)
+{
+    jk_lane_body<LA, LB, LC, LD, T>(a);
+}
+
+template <int LA, int LB, int LC, int LD, typename T, int W>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_jk_occ(JKLaunch a)
+{
+    jk_lane_body<LA, LB, LC, LD, T>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -873,7 +901,11 @@ template <int LA, int LB, int LC, int LD, typename T>
 int launch_plain(const JKLaunch &a, hipStream_t s)
 {
     if (a.nitems <= 0) return 0;
-    hipLaunchKernelGGL((k_jk<LA, LB, LC, LD, T>), dim3(a.nitems), dim3(64), 0, s, a);
+    constexpr int W = jk_waves<LA, LB, LC, LD>();
+    if constexpr (W > 0)
+        hipLaunchKernelGGL((k_jk_occ<LA, LB, LC, LD, T, W>), dim3(a.nitems), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_jk<LA, LB, LC, LD, T>), dim3(a.nitems), dim3(64), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
