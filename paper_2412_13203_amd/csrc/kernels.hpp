@@ -597,17 +597,48 @@ __global__ __launch_bounds__(64) void k_schwarz(SchwarzLaunch a)
 //   phase 1: each lane runs the vertical recurrence in NPASS passes over its
 //            quartet's primitive quartets; a pass keeps only its subset of
 //            accumulators in registers and writes them to a per-slot staging
-//            buffer in global memory ([target][lane], coalesced);
-//   phase 2: the wave takes the item's quartets one at a time: [e0|f0] into
-//            LDS, bra HRR one ket column per lane, ket HRR one (ab) row per
-//            lane, then the six digestion contractions one output element per
-//            lane, with the bra-uniform Jt_ab kept per lane across the item.
+//            buffer in global memory, quartet-major with the targets in pass
+//            order ([lane][pass, j]), through a 16-target LDS transpose so that
+//            the stores are coalesced;
+//   phase 2: the wave takes the item's quartets one at a time: [e0|f0] read
+//            contiguously and scattered into LDS in target order, bra HRR one
+//            ket column per lane, ket HRR one (ab) row per lane, then the six
+//            digestion contractions one output element per lane, with the
+//            bra-uniform Jt_ab kept per lane across the item.
+// (The gradient's split passes keep the [target][lane] layout: their HRR reads
+// the slot directly.)
 // Blocks are persistent (grid = staging slots) and stride over the items.
 // ---------------------------------------------------------------------------
-template <int LA, int LB, int LC, int LD, int P, typename T, int WK = WK_ONE>
+// first staging position of pass P (positions are in pass order)
+template <int LA, int LB, int LC, int LD, int P>
+__device__ constexpr int split_off()
+{
+    if constexpr (P == 0)
+        return 0;
+    else
+        return split_off<LA, LB, LC, LD, P - 1>() + EriSplit<LA, LB, LC, LD>::template npass_acc<P - 1>();
+}
+
+// target index of staging position s (pass order -> target order)
+template <int LA, int LB, int LC, int LD, int P = 0>
+__device__ __forceinline__ int split_target(int s)
+{
+    using S = EriSplit<LA, LB, LC, LD>;
+    if constexpr (P >= S::NPASS) {
+        return -1;
+    } else {
+        constexpr int o = split_off<LA, LB, LC, LD, P>(), n = S::template npass_acc<P>();
+        if (s < o + n) return S::template gmap<P>(s - o);
+        return split_target<LA, LB, LC, LD, P + 1>(s);
+    }
+}
+
+// QMAJOR = false: the slot is [target][lane] (gradient); true: [lane][position]
+// written through the wave's 16 x 65 LDS transpose buffer s_tr (J/K).
+template <int LA, int LB, int LC, int LD, int P, typename T, int WK = WK_ONE, bool QMAJOR = false>
 __device__ __forceinline__ void split_pass(const ShellPairD &bra, const ShellPairD &ket,
                                            const PrimPairD *__restrict__ prims, bool active,
-                                           double *__restrict__ stage, int lane)
+                                           double *__restrict__ stage, int lane, double *s_tr = nullptr)
 {
     using S = EriSplit<LA, LB, LC, LD>;
     constexpr int L = LA + LB + LC + LD;
@@ -627,24 +658,51 @@ __device__ __forceinline__ void split_pass(const ShellPairD &bra, const ShellPai
             S::template vrr<P, T>(Ft, h, acc);
         }
     });
-    // The lane offset is made opaque here so that the compiler cannot hoist
-    // one 64-bit store address per target out of the item loop (that many
-    // live addresses would be spilled to scratch).
-    int off = lane;
-    __asm__ volatile("" : "+v"(off));
-    double *sl = stage + off;
+    if constexpr (QMAJOR) {
+        // 16 positions at a time: lanes write their values to LDS, then each
+        // store instruction writes 16 consecutive positions of 4 quartets
+        // (lane-dependent offsets are made opaque, as below, so that the
+        // compiler does not keep one address per store live across the item
+        // loop)
+        constexpr int O = split_off<LA, LB, LC, LD, P>();
+        const int jj = lane & 15;
+        int qo = (lane >> 4) * S::NACC + O + jj, to = jj * 65 + (lane >> 4), lo = lane;
+        __asm__ volatile("" : "+v"(qo), "+v"(to), "+v"(lo));
+        double *sq = stage + qo;
+        const double *tr = s_tr + to;
+        double *tw = s_tr + lo;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) sl[S::template gmap<P>(j) * 64] = (double)acc[j];
+        for (int c0 = 0; c0 < NP; c0 += 16) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (c0 + j < NP) tw[j * 65] = (double)acc[c0 + j];
+            __syncthreads();
+            if (c0 + jj < NP) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) sq[4 * r * S::NACC + c0] = tr[4 * r];
+            }
+            __syncthreads();
+        }
+    } else {
+        // The lane offset is made opaque here so that the compiler cannot hoist
+        // one 64-bit store address per target out of the item loop (that many
+        // live addresses would be spilled to scratch).
+        int off = lane;
+        __asm__ volatile("" : "+v"(off));
+        double *sl = stage + off;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) sl[S::template gmap<P>(j) * 64] = (double)acc[j];
+    }
 }
 
-template <int LA, int LB, int LC, int LD, int P, typename T, int WK = WK_ONE>
+template <int LA, int LB, int LC, int LD, int P, typename T, int WK = WK_ONE, bool QMAJOR = false>
 __device__ __forceinline__ void split_passes(const ShellPairD &bra, const ShellPairD &ket,
                                              const PrimPairD *__restrict__ prims, bool active,
-                                             double *__restrict__ stage, int lane)
+                                             double *__restrict__ stage, int lane, double *s_tr = nullptr)
 {
     if constexpr (P < EriSplit<LA, LB, LC, LD>::NPASS) {
-        split_pass<LA, LB, LC, LD, P, T, WK>(bra, ket, prims, active, stage, lane);
-        split_passes<LA, LB, LC, LD, P + 1, T, WK>(bra, ket, prims, active, stage, lane);
+        split_pass<LA, LB, LC, LD, P, T, WK, QMAJOR>(bra, ket, prims, active, stage, lane, s_tr);
+        split_passes<LA, LB, LC, LD, P + 1, T, WK, QMAJOR>(bra, ket, prims, active, stage, lane, s_tr);
     }
 }
 
@@ -667,10 +725,15 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
     __shared__ double s_CD[64][3];
     __shared__ double s_w[64];
     __shared__ int s_ao[64][2];
+    __shared__ double s_tr[16 * 65];
     double *const s_Dcd = s_Dq, *const s_Dac = s_Dq + OAC, *const s_Dad = s_Dq + OAD, *const s_Dbc = s_Dq + OBC,
                   *const s_Dbd = s_Dq + OBD;
+    static_assert(split_off<LA, LB, LC, LD, S::NPASS>() == NACC, "passes must partition the targets");
     const int lane = threadIdx.x;
     double *stage = a.stage + (size_t)blockIdx.x * NACC * 64;
+    int tpos[KS];  // target of staging position lane + 64 k
+#pragma unroll
+    for (int k = 0; k < KS; ++k) tpos[k] = lane + 64 * k < NACC ? split_target<LA, LB, LC, LD>(lane + 64 * k) : 0;
 
     for (;;) {
         const int item = next_item(a, lane);
@@ -720,7 +783,7 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
             const int pos0 = __builtin_amdgcn_readfirstlane(__shfl(rk.pos, 0, 64));
             const int ket_pos = sg.ket_begin + (active ? rk.pos : pos0);
             const ShellPairD ket = ldg(sg.pairs + ket_pos);
-            split_passes<LA, LB, LC, LD, 0, T>(bra, ket, sg.prims, active, stage, lane);
+            split_passes<LA, LB, LC, LD, 0, T, WK_ONE, true>(bra, ket, sg.prims, active, stage, lane, s_tr);
             {
                 double s = 1.0;
                 if (bra.same) s *= 2.0;
@@ -744,7 +807,7 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
 #pragma unroll
                 for (int k = 0; k < KS; ++k) {
                     const int t = lane + 64 * k;
-                    pst[k] = t < NACC ? stage[(size_t)t * 64 + q] : 0.0;
+                    pst[k] = t < NACC ? stage[(size_t)q * NACC + t] : 0.0;
                 }
 #pragma unroll
                 for (int k = 0; k < KD; ++k) {
@@ -772,7 +835,7 @@ __global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
                 }
 #pragma unroll
                 for (int k = 0; k < KS; ++k)
-                    if (lane + 64 * k < NACC) s_buf[lane + 64 * k] = pst[k];
+                    if (lane + 64 * k < NACC) s_buf[tpos[k]] = pst[k];
 #pragma unroll
                 for (int k = 0; k < KD; ++k)
                     if (lane + 64 * k < NDQ) s_Dq[lane + 64 * k] = pdq[k];
