@@ -38,6 +38,7 @@ from __future__ import annotations
 
 import json
 import os
+import random
 import sys
 from dataclasses import dataclass, field
 
@@ -271,16 +272,43 @@ def choose_passes(la, lb, lc, ld, max_acc):
         per = max_acc // len(other)
         if per < 1:
             continue
+
+        def expand(g):
+            return [(e, f) for e in es for f in g] if side == "f" else [(e, f) for e in g for f in fs]
+
+        cost = {}
+
+        def group_flops(g):
+            if g not in cost:
+                cost[g] = best_vrr(la, lb, lc, ld, expand(g)).flops()
+            return cost[g]
+
         srt = sorted(items, key=_axis_key)
         ngrp = -(-len(srt) // per)
         # balanced contiguous groups
         bounds = [round(g * len(srt) / ngrp) for g in range(ngrp + 1)]
-        groups = [srt[bounds[g]:bounds[g + 1]] for g in range(ngrp)]
-        passes = [[(e, f) for e in es for f in g] if side == "f" else [(e, f) for e in g for f in fs]
-                  for g in groups]
-        tot = sum(best_vrr(la, lb, lc, ld, p).flops() for p in passes)
+        groups = [tuple(srt[bounds[g]:bounds[g + 1]]) for g in range(ngrp)]
+        tot = sum(group_flops(g) for g in groups)
+        # then a seeded local search: move one component to another group or
+        # swap two, kept when the summed flops of the passes drop
+        rng = random.Random((((la * 7 + lb) * 7 + lc) * 7 + ld) * 4096 + max_acc * 2 + (side == "e"))
+        for _ in range(PASS_SEARCH if ngrp > 1 else 0):
+            i, j = rng.sample(range(ngrp), 2)
+            gi, gj = list(groups[i]), list(groups[j])
+            if rng.random() < 0.5 and len(gj) < per and len(gi) > 1:
+                x = rng.choice(gi)
+                gi.remove(x)
+                gj.append(x)
+            else:
+                x, y = rng.choice(gi), rng.choice(gj)
+                gi[gi.index(x)] = y
+                gj[gj.index(y)] = x
+            ni, nj = tuple(sorted(gi, key=_axis_key)), tuple(sorted(gj, key=_axis_key))
+            new = tot - group_flops(groups[i]) - group_flops(groups[j]) + group_flops(ni) + group_flops(nj)
+            if new < tot:
+                groups[i], groups[j], tot = ni, nj, new
         if best is None or tot < best[0]:
-            best = (tot, passes)
+            best = (tot, [expand(g) for g in groups])
     if best is None:
         raise ValueError("max_acc too small for this class")
     return best[1]
@@ -343,6 +371,9 @@ def cls_name(la, lb, lc, ld):
 
 # classes whose accumulators exceed this many doubles run as several passes
 MAX_ACC = int(os.environ.get("MJK_MAX_ACC", "96"))
+# local-search steps over the pass groups of a split class (0: the plain
+# contiguous groups)
+PASS_SEARCH = int(os.environ.get("MJK_PASS_SEARCH", "400"))
 # the same for the shifted classes only the nuclear gradient uses (one unit
 # of angular momentum higher: more recurrence intermediates per target)
 GRAD_MAX_ACC = int(os.environ.get("MJK_GRAD_MAX_ACC", "64"))
