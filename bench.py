@@ -198,7 +198,7 @@ def grad_comparison(torch, mjk, inputs, dev, steps=2, warmup=1):
     }
 
 
-def batch_comparison(torch, mjk, inputs, dev, nmol=64, atom_range=(8, 32), steps=2):
+def batch_comparison(torch, mjk, inputs, dev, nmol=64, atom_range=(8, 32), steps=2, tune_reps=2):
     """Many molecules of uneven size: sequential single-molecule FP64 builds
     (default tiles) vs one batch (one launch per class over all molecules),
     with default tiles and with the tiles Algorithm 2 picks on this batch."""
@@ -209,15 +209,22 @@ def batch_comparison(torch, mjk, inputs, dev, nmol=64, atom_range=(8, 32), steps
     ev1 = torch.cuda.Event(enable_timing=True)
     # sequential: one plan per molecule, plans built before timing
     plans = [mjk.Plan(m["basis"], tau=tau, device=dev) for m in mols]
+    print(f"bench: {nmol} single-molecule plans bound", file=sys.stderr, flush=True)
     Ds = [torch.as_tensor(m["D"], device=f"cuda:{dev}") for m in mols]
     outs = [(torch.empty_like(D), torch.empty_like(D)) for D in Ds]
-    for p, D, (J, K) in zip(plans, Ds, outs):
-        p.build_jk(D, J, K)
+    def seq_pass(what):
+        # a progress line every 16 molecules (the full atom range takes minutes)
+        for i, (p, D, (J, K)) in enumerate(zip(plans, Ds, outs)):
+            p.build_jk(D, J, K)
+            if (i + 1) % 16 == 0:
+                torch.cuda.synchronize()
+                print(f"bench: {what}, molecule {i + 1} of {nmol}", file=sys.stderr, flush=True)
+
+    seq_pass("sequential warm-up")
     torch.cuda.synchronize()
     ev0.record()
-    for _ in range(steps):
-        for p, D, (J, K) in zip(plans, Ds, outs):
-            p.build_jk(D, J, K)
+    for s_ in range(steps):
+        seq_pass(f"sequential pass {s_ + 1} of {steps}")
     ev1.record()
     torch.cuda.synchronize()
     seq_ms = ev0.elapsed_time(ev1) / steps
@@ -227,6 +234,7 @@ def batch_comparison(torch, mjk, inputs, dev, nmol=64, atom_range=(8, 32), steps
     bt = mjk.Batch([m["basis"] for m in mols], tau=tau, device=dev)
     torch.cuda.synchronize()
     plan_ms = (time.time() - t0) * 1e3
+    print(f"bench: sequential {seq_ms:.1f} ms; batch plan bound in {plan_ms:.0f} ms", file=sys.stderr, flush=True)
     D = bt.pack([m["D"] for m in mols])
     J = torch.empty_like(D)
     K = torch.empty_like(D)
@@ -234,6 +242,7 @@ def batch_comparison(torch, mjk, inputs, dev, nmol=64, atom_range=(8, 32), steps
     def timed():
         bt.build_jk(D, J, K)
         torch.cuda.synchronize()
+        print("bench: batch warm-up build done", file=sys.stderr, flush=True)
         ev0.record()
         for _ in range(steps):
             bt.build_jk(D, J, K)
@@ -242,10 +251,15 @@ def batch_comparison(torch, mjk, inputs, dev, nmol=64, atom_range=(8, 32), steps
         return ev0.elapsed_time(ev1) / steps
 
     default_ms = timed()
+    print(f"bench: batch with default tiles {default_ms:.1f} ms", file=sys.stderr, flush=True)
     t0 = time.time()
-    qpl = bt.autotune(D, reps=2)
+    if tune_reps > 0:
+        qpl = bt.autotune(D, reps=tune_reps)
+        tuned_ms = timed()
+    else:
+        qpl = [1] * mjk.num_classes()
+        tuned_ms = default_ms
     tune_s = time.time() - t0
-    tuned_ms = timed()
     bt.set_stamps(True)
     bt.build_jk(D, J, K)
     torch.cuda.synchronize()
@@ -263,7 +277,7 @@ def batch_comparison(torch, mjk, inputs, dev, nmol=64, atom_range=(8, 32), steps
         "sequential_ms": seq_ms, "sequential_quartets_per_s": nq / (seq_ms * 1e-3),
         "batch_default_ms": default_ms, "batch_tuned_ms": tuned_ms,
         "batch_quartets_per_s": bt.stats["nquartet_kept"] / (tuned_ms * 1e-3),
-        "speedup_vs_sequential": seq_ms / tuned_ms, "autotune_s": tune_s,
+        "speedup_vs_sequential": seq_ms / tuned_ms, "autotune_s": tune_s, "autotuned": tune_reps > 0,
         "tuned_quartets_per_lane": {names[q]: v for q, v in enumerate(qpl) if v != 1},
         "per_molecule_ms": {"min": dur[0], "median": dur[len(dur) // 2], "max": dur[-1]},
         "finish_spread_ms": ends[-1] - ends[0],
@@ -283,6 +297,11 @@ def main():
                     help="skip the 60-atom nuclear-gradient timing (backward / forward ratio)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-molecule batched build (one launch per class, autotuned tiles)")
+    ap.add_argument("--batch-atoms", type=int, nargs=2, default=[8, 32], metavar=("LO", "HI"),
+                    help="atom-count range of the batch's molecules (the full recipe is 8 96)")
+    ap.add_argument("--batch-steps", type=int, default=2, help="timed builds per batch measurement")
+    ap.add_argument("--batch-tune-reps", type=int, default=2,
+                    help="builds per autotuner trial (0: no autotuning, default tiles only)")
     ap.add_argument("--fp32-tau", type=float, nargs="+", default=[1e-4, 1e-6],
                     help="mixed-precision thresholds for --mixed (first one is the headline)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -412,7 +431,8 @@ def main():
     if not args.no_grad:
         out["grad"] = grad_comparison(torch, mjk, inputs, dev)
     if not args.no_batch:
-        out["batch"] = batch_comparison(torch, mjk, inputs, dev)
+        out["batch"] = batch_comparison(torch, mjk, inputs, dev, atom_range=tuple(args.batch_atoms),
+                                        steps=args.batch_steps, tune_reps=args.batch_tune_reps)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)
