@@ -62,9 +62,12 @@ def measured_traffic(cls):
     return rec["fetch_bytes"] + rec["write_bytes"]
 
 
-def cpu_baseline(cfg, target_s=15.0):
-    """Oracle quartets/s on a sample: bra pairs at a fixed stride of the
-    unique-quartet list, every kept ket of each (same screening rule)."""
+def cpu_baseline(cfg, nbra=32):
+    """Oracle quartets/s on a sample: nbra bra pairs at a fixed stride of the
+    unique-quartet list, every kept ket of each (same screening rule).  The
+    cost of one bra pair varies by orders of magnitude with its class, so the
+    sample is a fixed, evenly spread set (~15 s on 16 host threads), not one
+    sized from a timing probe."""
     import oracle
     b, D, tau = cfg["basis"], cfg["D"], cfg["tau"]
     ns = len(b["shell_l"])
@@ -72,18 +75,11 @@ def cpu_baseline(cfg, target_s=15.0):
     t0 = time.time()
     Q = oracle.schwarz(b)
     t_q = time.time() - t0
-    # probe one row to size the sample
-    stride = 4096
+    stride = max(1, npair // nbra)
     rows = np.arange(stride // 2, npair, stride, dtype=np.int32)
     t0 = time.time()
     _, _, nq = oracle.jk_rows(b, D, tau, rows, Q)
     dt = time.time() - t0
-    if dt < target_s / 2:
-        stride = max(8, int(stride * max(dt, 1e-3) / target_s))
-        rows = np.arange(stride // 2, npair, stride, dtype=np.int32)
-        t0 = time.time()
-        _, _, nq = oracle.jk_rows(b, D, tau, rows, Q)
-        dt = time.time() - t0
     return {
         "value": nq / dt, "unit": "quartets/s", "cores": oracle.nthreads(), "kind": "oracle",
         "sample": f"{len(rows)} bra pairs (every {stride}th of {npair}), all kept kets: {nq} quartets in "

@@ -709,7 +709,7 @@ __device__ __forceinline__ void split_passes(const ShellPairD &bra, const ShellP
 // T = float: the passes run the recurrence and the contraction in FP32 and
 // stage the contracted values as FP64; HRR and digestion are FP64.
 template <int LA, int LB, int LC, int LD, typename T>
-__global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
+__device__ __forceinline__ void jk_split_body(const JKLaunch &a)
 {
     using S = EriSplit<LA, LB, LC, LD>;
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
@@ -944,19 +944,40 @@ int persistent_grid(K kernel, size_t lds, int nitems, int nslot, bool staged)
 }
 
 template <int LA, int LB, int LC, int LD, typename T>
+__global__ __launch_bounds__(64) void k_jk_split(JKLaunch a)
+{
+    jk_split_body<LA, LB, LC, LD, T>(a);
+}
+
+// The FP32 split kernels need a little over 256 VGPRs; asking for two
+// resident waves per SIMD trades a few spills for twice the occupancy.
+template <int LA, int LB, int LC, int LD, typename T, int W>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_jk_split_occ(JKLaunch a)
+{
+    jk_split_body<LA, LB, LC, LD, T>(a);
+}
+
+template <int LA, int LB, int LC, int LD, typename T>
 int launch_split(const JKLaunch &a, hipStream_t s)
 {
     if (a.nitems <= 0) return 0;
+    constexpr bool OCC = sizeof(T) == sizeof(float);
     static int grid_cache = 0;  // occupancy bound, computed once
     if (grid_cache == 0) {
-        grid_cache = persistent_grid(k_jk_split<LA, LB, LC, LD, T>, 0, 1 << 30, 1 << 30, false);
+        if constexpr (OCC)
+            grid_cache = persistent_grid(k_jk_split_occ<LA, LB, LC, LD, T, 2>, 0, 1 << 30, 1 << 30, false);
+        else
+            grid_cache = persistent_grid(k_jk_split<LA, LB, LC, LD, T>, 0, 1 << 30, 1 << 30, false);
         if (grid_cache <= 0) return -1;
     }
     int grid = grid_cache;
     if (grid > a.nslot) grid = a.nslot;
     if (grid > a.nitems) grid = a.nitems;
     if (grid < 1) return -1;
-    hipLaunchKernelGGL((k_jk_split<LA, LB, LC, LD, T>), dim3(grid), dim3(64), 0, s, a);
+    if constexpr (OCC)
+        hipLaunchKernelGGL((k_jk_split_occ<LA, LB, LC, LD, T, 2>), dim3(grid), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_jk_split<LA, LB, LC, LD, T>), dim3(grid), dim3(64), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
