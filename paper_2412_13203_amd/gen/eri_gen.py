@@ -375,8 +375,13 @@ MAX_ACC = int(os.environ.get("MJK_MAX_ACC", "96"))
 # contiguous groups)
 PASS_SEARCH = int(os.environ.get("MJK_PASS_SEARCH", "400"))
 # the same for the shifted classes only the nuclear gradient uses (one unit
-# of angular momentum higher: more recurrence intermediates per target)
+# of angular momentum higher: more recurrence intermediates per target).
+# Measured on the 60-atom gradient: 96-target passes are faster up to
+# L = 7 ((dp|ds)'s kernel 1.03 -> 0.93 s), 64-target ones from L = 8 on
+# ((dd|dp) 1.23 vs 1.27 s, (dd|dd) 0.70 vs 0.76 s).
 GRAD_MAX_ACC = int(os.environ.get("MJK_GRAD_MAX_ACC", "64"))
+GRAD_MAX_ACC_LOW_L = int(os.environ.get("MJK_GRAD_MAX_ACC_LOW_L", "96"))
+GRAD_LOW_L_MAX = 7
 # a compiler scheduling fence every this many recurrence nodes keeps the
 # low-pressure emission order (0 = no fences)
 SCHED_WINDOW = int(os.environ.get("MJK_SCHED_WINDOW", "0"))
@@ -785,7 +790,8 @@ def _write(path, text):
 def _class_job(args):
     """Emit one class header; returns its name, text and counts."""
     (la, lb, lc, ld), (fwd, grad) = args
-    cc = ClassCode(la, lb, lc, ld, max_acc=MAX_ACC if fwd else GRAD_MAX_ACC, passes=grad)
+    gmax = GRAD_MAX_ACC_LOW_L if la + lb + lc + ld <= GRAD_LOW_L_MAX else GRAD_MAX_ACC
+    cc = ClassCode(la, lb, lc, ld, max_acc=MAX_ACC if fwd else gmax, passes=grad)
     # a class the J/K path runs keeps its single-pass code (eri_class and
     # Schwarz use it); a split class used only by the gradient needs passes
     full = fwd or not cc.split
