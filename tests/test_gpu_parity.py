@@ -205,3 +205,22 @@ def test_screening_changes_counts_consistently():
         assert plan.stats["nquartet_kept"] == nq
         _close(_np(J), Jo)
         _close(_np(K), Ko)
+
+
+def test_run_records_across_chunk_sizes():
+    """Kets are numbered through per-bra run records (one run per first
+    shell, each cut to its kept prefix).  Screening at 1e-6 leaves many
+    partial runs; 1, 4 and 16 quartets per lane move the chunk and round
+    boundaries to different places inside runs.  Every choice must give the
+    oracle's J and K."""
+    cfg = inputs.make_config(2, natom=8)
+    b, D = cfg["basis"], cfg["D"]
+    tau = 1e-6
+    Jo, Ko, nq = oracle.build_jk(b, D, tau)
+    plan = mjk.Plan(b, tau=tau)
+    assert plan.stats["nquartet_kept"] == nq
+    for q in (1, 4, 16):
+        plan.set_tiles([q] * mjk.num_classes())
+        J, K = plan.build_jk(D)
+        _close(_np(J), Jo, what=f"J (qpl {q})")
+        _close(_np(K), Ko, what=f"K (qpl {q})")
