@@ -308,3 +308,64 @@ def test_overlap_closed_form():
     p = 3.2
     R2 = 0.16 + 0.09 + 1.21
     assert abs(S - (math.pi / p) ** 1.5 * math.exp(-0.9 * 2.3 / p * R2)) < 1e-15
+
+
+def test_schwarz_value_is_sqrt_of_largest_diagonal():
+    """Pins orc_schwarz's value, not only its bound: Q_AB = sqrt(max over the
+    components a in A, b in B of the diagonal integral (ab|ab)), for every
+    shell pair of a small s, p, d basis (the contracted blocks come from
+    eri_block, itself pinned above).  A sum in place of the max, an
+    off-diagonal element or a missing square root fails here; the basis is
+    rescaled so that some diagonal integrals exceed 1, where a missing
+    square root would otherwise hide behind values below 1."""
+    b = _random_basis(21, ls=(0, 1, 2), natom=3)
+    b = dict(b)
+    b["coefs"] = np.asarray(b["coefs"]) * 3.0
+    Q = oracle.schwarz(b)
+    ns = len(b["shell_l"])
+    assert np.array_equal(Q, Q.T)
+    above_one = 0
+    for A in range(ns):
+        for B in range(A + 1):
+            blk = oracle.eri_block(b, A, B, A, B)
+            na, nb = blk.shape[:2]
+            diag = np.array([blk[i, j, i, j] for i in range(na) for j in range(nb)])
+            assert np.all(diag > 0)
+            above_one += int(diag.max() > 1.0)
+            ref = math.sqrt(float(diag.max()))
+            assert abs(Q[A, B] - ref) <= 1e-15 * ref, (A, B, Q[A, B], ref)
+    assert above_one > 0
+
+
+def test_schwarz_closed_form_primitives():
+    """Pins orc_schwarz against the closed form, independently of the oracle's
+    integrals: for single primitives with coefficient c, Q_AB^2 is
+    c_a^2 c_b^2 [ab|ab]; for two s shells that is the [ss|ss] closed form,
+    and for a p shell on A and an s shell on B it is the largest of the three
+    [p_i s|p_i s], each a centre derivative of the closed form (mpmath).
+    The coefficients make the values exceed 1."""
+    rng = np.random.default_rng(33)
+    for _ in range(3):
+        cen = _rand_geom(rng, n=2, box=1.5)
+        ex = np.exp(rng.uniform(np.log(0.3), np.log(4.0), size=2))
+        ca, cb = 2.5, 1.7
+        # s s
+        bs = prim_basis(cen, ex, (0, 0))
+        bs["coefs"] = np.array([ca, cb])
+        Q = oracle.schwarz(bs)
+        ref = ca * cb * math.sqrt(ssss_closed(cen[0], cen[1], cen[0], cen[1], ex[0], ex[1], ex[0], ex[1]))
+        assert ref > 1.0
+        assert abs(Q[0, 1] - ref) <= 1e-13 * ref
+        # p s: max over the three components of [p_i s | p_i s]
+        bp = prim_basis(cen, ex, (1, 0))
+        bp["coefs"] = np.array([ca, cb])
+        Qp = oracle.schwarz(bp)
+        four = [cen[0], cen[1], cen[0], cen[1]]
+        exs = [ex[0], ex[1], ex[0], ex[1]]
+        vals = []
+        for i in range(3):
+            e = [0, 0, 0]
+            e[i] = 1
+            vals.append(prim_eri_by_derivatives(four, exs, [tuple(e), (0, 0, 0), tuple(e), (0, 0, 0)]))
+        refp = ca * cb * math.sqrt(max(vals))
+        assert abs(Qp[0, 1] - refp) <= 1e-11 * refp, (Qp[0, 1], refp)
