@@ -16,7 +16,8 @@
  *
  * Conventions shared by every call:
  *   - Units are bohr.  Real Cartesian functions, chemists' notation.
- *   - Shells: l in 0..3, 1..6 primitives.  Coefficients are final: they
+ *   - Shells: l in 0..mjk_lmax() (3 in this build), 1..6 primitives.  The
+ *     nuclear gradient takes l <= mjk_grad_lmax().  Coefficients are final: they
  *     multiply the unnormalized primitive x^i y^j z^k exp(-alpha r^2); the
  *     library never normalizes.
  *   - AO order: shells in input order; inside a shell the Cartesian
@@ -29,9 +30,10 @@
  *     Work calls are asynchronous on it unless stated otherwise.
  *   - Every function returns an int status: MJK_OK (0) or a negative error
  *     code; mjk_last_error() gives the message of the last failure on the
- *     calling thread.  No exception crosses the ABI.  Arguments are checked
- *     on the host before any launch; a device fault surfaces at the next call
- *     that synchronizes.
+ *     calling thread, mjk_ctx_last_error(ctx) that of the last failed call
+ *     made with a context (directly or through its plans and batches).  No
+ *     exception crosses the ABI.  Arguments are checked on the host before
+ *     any launch; a device fault surfaces at the next call that synchronizes.
  */
 #ifndef MJK_H
 #define MJK_H
@@ -49,7 +51,8 @@ extern "C" {
 #define MJK_ERR_NO_DEVICE (-3)    /* no HIP device, or not a gfx950 device                */
 #define MJK_ERR_WORKSPACE (-4)    /* workspace pointer null, misaligned or too small      */
 #define MJK_ERR_HIP (-5)          /* a HIP runtime call failed                            */
-#define MJK_ERR_STATE (-6)        /* call out of order (e.g. build before bind)           */
+#define MJK_ERR_STATE (-6)        /* call out of order (e.g. build before bind), or a      *
+                                   * staging region too small for a launch's blocks       */
 
 /* Flags of mjk_jk_opts.flags */
 #define MJK_FLAG_CHECK 0x1u       /* check D on the host side of the call: finite and symmetric */
@@ -66,7 +69,7 @@ typedef struct mjk_basis {
     const double *xyz;            /* natom x 3, bohr                         */
     int32_t nshell;
     const int32_t *shell_atom;    /* nshell, 0..natom-1                      */
-    const int32_t *shell_l;       /* nshell, 0..3                            */
+    const int32_t *shell_l;       /* nshell, 0..mjk_lmax()                   */
     const int32_t *shell_nprim;   /* nshell, 1..6                            */
     const int32_t *shell_prim_off;/* nshell, offset into exps / coefs        */
     int64_t nprim;                /* length of exps and coefs                */
@@ -106,8 +109,11 @@ typedef struct mjk_plan_stats {
     double grad_flops_kept;     /* algorithmic flops of mjk_grad_e2 (MJK_FLAG_GRAD) */
 } mjk_plan_stats;
 
-/* Library identification: lmax of the build (highest shell l supported). */
+/* Library identification: lmax of the build (highest shell l supported by
+ * the J/K build, eri_class and the Schwarz factors) and the highest shell l
+ * the nuclear gradient supports (its shifted classes reach one more). */
 int mjk_lmax(void);
+int mjk_grad_lmax(void);
 
 /* Quartet classes of the build: classes (la lb | lc ld) with la >= lb,
  * lc >= ld and pair class (la, lb) >= (lc, ld), indexed X(X+1)/2 + Y over
@@ -118,6 +124,11 @@ int mjk_class_l(int32_t q, int32_t *l4);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *mjk_last_error(void);
+
+/* Message of the last failed call made with `ctx` or one of its plans or
+ * batches, on any thread ("" if none).  The pointer stays valid on the
+ * calling thread until its next call of this function. */
+const char *mjk_ctx_last_error(mjk_ctx *ctx);
 
 /* Context on HIP device `device` (must be gfx950).  Returns MJK_ERR_NO_DEVICE
  * when no such device exists. */
@@ -154,6 +165,14 @@ int mjk_build_jk(mjk_plan *plan, const double *D, double *J, double *K, void *st
  * nbf x nbf; e2: one device float64, overwritten.  Asynchronous. */
 int mjk_e2(mjk_plan *plan, const double *D, const double *J, const double *K, double *e2, void *stream);
 
+/* Boys function F_m(T) = int_0^1 t^{2m} exp(-T t^2) dt, m = 0..mmax, by the
+ * device routine of the class kernels (Section 2.2: the recurrences start
+ * from an analytic [00|00], which is a prefactor times F_m(T)).
+ * T: device float64, n values (finite, >= 0; any other value gives NaN
+ * rows).  F: device float64, n x (mmax + 1), row-major, overwritten.
+ * mmax in 0..13 (MJK_ERR_UNSUPPORTED otherwise).  Asynchronous on `stream`. */
+int mjk_boys(mjk_ctx *ctx, int32_t mmax, const double *T, int64_t n, double *F, void *stream);
+
 /* Nuclear gradient of E2 at fixed D: grad[3*atom + i] = dE2/dR_{atom,i},
  * device float64 natom x 3, overwritten.  The basis functions move with
  * their atoms; d(ab|cd)/dA_i = 2 alpha (a+1_i b|cd) - a_i (a-1_i b|cd) on
@@ -164,6 +183,19 @@ int mjk_e2(mjk_plan *plan, const double *D, const double *J, const double *K, do
  * limited to 1024 (MJK_ERR_UNSUPPORTED).  Asynchronous on `stream`; with
  * timing enabled the per-class events cover this call's launches. */
 int mjk_grad_e2(mjk_plan *plan, const double *D, double *grad, void *stream);
+
+/* Backward of E2 = 1/2 Tr(DJ) - 1/4 Tr(DK) for automatic differentiation,
+ * scaled by the upstream gradient: gout is one device float64 (dL/dE2), or
+ * NULL for 1.
+ *   gD (nbf x nbf, device float64, overwritten; NULL to skip):
+ *       gout * (J - K/2), the derivative with respect to the entries of a
+ *       symmetric D taken as independent (J and K are linear in D);
+ *       needs J and K of that D (mjk_build_jk); must not alias them.
+ *   gR (natom x 3, device float64, overwritten; NULL to skip):
+ *       gout * dE2/dR at fixed D, as mjk_grad_e2 (MJK_FLAG_GRAD plans).
+ * Asynchronous on `stream`. */
+int mjk_e2_backward(mjk_plan *plan, const double *D, const double *J, const double *K, const double *gout,
+                    double *gD, double *gR, void *stream);
 
 /* Per-class work per lane (Section 7, Algorithm 2's workload): qpl[q]
  * quartets per lane for class q (1, 2, 4, 8 or 16; n = mjk_num_classes()),

@@ -1,7 +1,9 @@
 // device_util.hip -- the small non-class kernels: primitive-pair table,
-// fill and in-place symmetrization.
+// fill, in-place symmetrization, E2 and its backward, and the Boys function
+// evaluated on its own.
 #include <hip/hip_runtime.h>
 
+#include "kernels.hpp"
 #include "mjk_types.hpp"
 
 namespace mjk {
@@ -157,6 +159,85 @@ int launch_symmetrize(double *M, int n, hipStream_t s)
     const unsigned g = (unsigned)((n + 15) / 16);
     hipLaunchKernelGGL(k_symmetrize, dim3(g, g), dim3(256), 0, s, M, n);
     return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// dE2/dD = g (J - K/2): E2 = 1/2 Tr(DJ) - 1/4 Tr(DK) with J and K linear in
+// D, so the derivative with respect to the entries of a symmetric D (taken
+// as independent) is J - K/2; g is the upstream gradient (device scalar,
+// NULL = 1).
+__global__ __launch_bounds__(256) void k_e2_grad_D(const double *__restrict__ J, const double *__restrict__ K,
+                                                   const double *__restrict__ g, double *__restrict__ out, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const double s = g ? *g : 1.0;
+    out[t] = s * (J[t] - 0.5 * K[t]);
+}
+
+__global__ __launch_bounds__(256) void k_scale(double *__restrict__ x, int64_t n, const double *__restrict__ g)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[t] *= *g;
+}
+
+int launch_e2_grad_D(const double *J, const double *K, const double *g, double *out, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_e2_grad_D, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, J, K, g, out, n);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_scale(double *x, int64_t n, const double *g, hipStream_t s)
+{
+    if (n <= 0 || !g) return 0;
+    hipLaunchKernelGGL(k_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, g);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// F_m(T), m = 0..M, by the same device routine the class kernels call with
+// L = M (Section 2.2's analytic [00|00]); one argument per thread.  T must be
+// finite and >= 0: any other argument gives NaN rather than a table read.
+template <int M>
+__global__ __launch_bounds__(256) void k_boys(const double *__restrict__ T, int64_t n, double *__restrict__ F)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const double x = T[t];
+    double f[M + 1];
+    if (x >= 0.0 && x <= 1.0e300) {
+        boys_fm<M>(x, f);
+    } else {
+#pragma unroll
+        for (int m = 0; m <= M; ++m) f[m] = __builtin_nan("");
+    }
+#pragma unroll
+    for (int m = 0; m <= M; ++m) F[t * (M + 1) + m] = f[m];
+}
+
+template <int M>
+int launch_boys_m(const double *T, int64_t n, double *F, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_boys<M>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, T, n, F);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int M>
+int launch_boys_upto(int mmax, const double *T, int64_t n, double *F, hipStream_t s)
+{
+    if (mmax == M) return launch_boys_m<M>(T, n, F, s);
+    if constexpr (M > 0)
+        return launch_boys_upto<M - 1>(mmax, T, n, F, s);
+    else
+        return -1;
+}
+
+int boys_lmax() { return MJK_BOYS_LMAX; }
+
+int launch_boys(int mmax, const double *T, int64_t n, double *F, hipStream_t s)
+{
+    if (n <= 0) return 0;
+    if (mmax < 0 || mmax > MJK_BOYS_LMAX) return -1;
+    return launch_boys_upto<MJK_BOYS_LMAX>(mmax, T, n, F, s);
 }
 
 }  // namespace mjk

@@ -471,16 +471,17 @@ int launch_grad(const JKLaunch &a, hipStream_t s)
     static size_t cached_lds = (size_t)-1;
     static int grid_cache = 0;
     if (cached_lds != lds) {
-        grid_cache = persistent_grid(k_grad<LA, LB, LC, LD>, lds, 1 << 30, 1 << 30, false);
-        if (grid_cache <= 0) return -1;
+        grid_cache = occupancy_grid(k_grad<LA, LB, LC, LD>, lds);
+        if (grid_cache <= 0) return kLaunchHip;
         cached_lds = lds;
     }
-    int grid = grid_cache;
-    if (grad_stage_nacc<LA, LB, LC, LD>() > 0 && grid > a.nslot) grid = a.nslot;
-    if (grid > a.nitems) grid = a.nitems;
-    if (grid < 1) return -1;
-    hipLaunchKernelGGL((k_grad<LA, LB, LC, LD>), dim3(grid), dim3(64), lds, s, a);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+    // a block with split shifted classes stages them in its own slot of
+    // grad_stage_nacc x 64 doubles (blocks stride over the items)
+    constexpr int64_t slot = (int64_t)grad_stage_nacc<LA, LB, LC, LD>() * 64;
+    const int64_t grid = persistent_blocks(grid_cache, a.nslot, a.nitems, slot > 0);
+    if (grid < 1 || !staging_fits(grid, slot, a.stage_bytes)) return kLaunchStaging;
+    hipLaunchKernelGGL((k_grad<LA, LB, LC, LD>), dim3((unsigned)grid), dim3(64), lds, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : kLaunchHip;
 }
 
 #define MJK_DEFINE_GRAD(LA, LB, LC, LD, NAME)                                                       \

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include "mjk_types.hpp"
+#include "stage_guard.hpp"
 
 namespace mjk {
 
@@ -926,21 +927,18 @@ __device__ __forceinline__ void jk_split_body(const JKLaunch &a)
     }
 }
 
-// Persistent grid for kernels that pop items from the launch's counter:
-// resident blocks per CU (occupancy) x CUs, at most one block per staging
-// slot and per item.
+// Occupancy bound of a persistent kernel: resident blocks per CU x CUs
+// (-1 if the device cannot be queried).  The launch grid is this bound cut
+// by persistent_blocks() to the staging slots and the work items.
 template <typename K>
-int persistent_grid(K kernel, size_t lds, int nitems, int nslot, bool staged)
+int occupancy_grid(K kernel, size_t lds)
 {
     int dev = 0, ncu = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return -1;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, lds) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    int grid = per_cu * ncu;
-    if (staged && grid > nslot) grid = nslot;
-    if (grid > nitems) grid = nitems;
-    return grid;
+    return per_cu * ncu;
 }
 
 template <int LA, int LB, int LC, int LD, typename T>
@@ -965,20 +963,20 @@ int launch_split(const JKLaunch &a, hipStream_t s)
     static int grid_cache = 0;  // occupancy bound, computed once
     if (grid_cache == 0) {
         if constexpr (OCC)
-            grid_cache = persistent_grid(k_jk_split_occ<LA, LB, LC, LD, T, 2>, 0, 1 << 30, 1 << 30, false);
+            grid_cache = occupancy_grid(k_jk_split_occ<LA, LB, LC, LD, T, 2>, 0);
         else
-            grid_cache = persistent_grid(k_jk_split<LA, LB, LC, LD, T>, 0, 1 << 30, 1 << 30, false);
-        if (grid_cache <= 0) return -1;
+            grid_cache = occupancy_grid(k_jk_split<LA, LB, LC, LD, T>, 0);
+        if (grid_cache <= 0) return kLaunchHip;
     }
-    int grid = grid_cache;
-    if (grid > a.nslot) grid = a.nslot;
-    if (grid > a.nitems) grid = a.nitems;
-    if (grid < 1) return -1;
+    // every block stages one item's [e0|f0] in its own slot of NACC x 64 doubles
+    const int64_t grid = persistent_blocks(grid_cache, a.nslot, a.nitems, true);
+    if (grid < 1 || !staging_fits(grid, (int64_t)EriSplit<LA, LB, LC, LD>::NACC * 64, a.stage_bytes))
+        return kLaunchStaging;
     if constexpr (OCC)
-        hipLaunchKernelGGL((k_jk_split_occ<LA, LB, LC, LD, T, 2>), dim3(grid), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((k_jk_split_occ<LA, LB, LC, LD, T, 2>), dim3((unsigned)grid), dim3(64), 0, s, a);
     else
-        hipLaunchKernelGGL((k_jk_split<LA, LB, LC, LD, T>), dim3(grid), dim3(64), 0, s, a);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+        hipLaunchKernelGGL((k_jk_split<LA, LB, LC, LD, T>), dim3((unsigned)grid), dim3(64), 0, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : kLaunchHip;
 }
 
 template <int LA, int LB, int LC, int LD, typename T>

@@ -21,12 +21,14 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "mjk.h"
 #include "gen/dispatch.inc"
 #include "mjk_types.hpp"
+#include "stage_guard.hpp"
 
 namespace mjk {
 int launch_pair_table(const ShellPairD *pairs, int npair, const double *xyz, const int32_t *atom,
@@ -37,13 +39,26 @@ int launch_symmetrize(double *M, int n, hipStream_t s);
 int launch_e2(const double *D, const double *J, const double *K, int n, double *e2, hipStream_t s);
 int launch_fill_u32(uint32_t *x, int64_t n, uint32_t v, hipStream_t s);
 int launch_stamp_init(unsigned long long *x, int n, hipStream_t s);
+int launch_e2_grad_D(const double *J, const double *K, const double *g, double *out, int64_t n, hipStream_t s);
+int launch_scale(double *x, int64_t n, const double *g, hipStream_t s);
+int launch_boys(int mmax, const double *T, int64_t n, double *F, hipStream_t s);
+int boys_lmax();
 }  // namespace mjk
 
 using namespace mjk;
 
+struct mjk_ctx {
+    int device;
+    std::string arch;
+    int ncu;
+    std::mutex err_mu;  // last failure of a call made with this context
+    std::string err;
+};
+
 namespace {
 
 thread_local std::string g_err;
+thread_local mjk_ctx *g_cur_ctx = nullptr;  // context of the call running on this thread
 
 int fail(int code, const char *fmt, ...)
 {
@@ -53,8 +68,20 @@ int fail(int code, const char *fmt, ...)
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     g_err = buf;
+    if (g_cur_ctx) {
+        std::lock_guard<std::mutex> lk(g_cur_ctx->err_mu);
+        g_cur_ctx->err = buf;
+    }
     return code;
 }
+
+// Marks the context of an entry point for its duration, so that a failure
+// is recorded on that context as well as on the calling thread.
+struct CtxScope {
+    mjk_ctx *prev;
+    explicit CtxScope(mjk_ctx *c) : prev(g_cur_ctx) { g_cur_ctx = c; }
+    ~CtxScope() { g_cur_ctx = prev; }
+};
 
 #define HIP_TRY(call)                                                                          \
     do {                                                                                       \
@@ -117,12 +144,6 @@ inline double prim_overhead_flops(int L) { return 26.0 + 4.0 * 7 + 2.0 + 3.0 * L
 
 }  // namespace
 
-struct mjk_ctx {
-    int device;
-    std::string arch;
-    int ncu;
-};
-
 namespace {
 
 // One launch: the segments of one quartet class at one precision.
@@ -167,6 +188,7 @@ struct mjk_plan {
     int64_t max_items = 0;    // upper bound of the items of one segment (one quartet per lane)
     size_t work_ints = 0;
     bool in_batch = false;    // staging and launches belong to a batch
+    size_t stage_bytes() const { return sizeof(double) * 64 * stage_nacc * (size_t)nslot; }
     char *ws = nullptr;
     bool bound = false;
     mjk_plan_stats stats{};
@@ -193,6 +215,7 @@ struct mjk_batch {
     char *ws = nullptr;
     bool bound = false;
     bool stamps = false, stamped_last = false;
+    size_t stage_bytes() const { return sizeof(double) * 64 * stage_nacc * (size_t)nslot; }
     bool timing = false, timed_last = false;
     std::vector<hipEvent_t> ev;
     ~mjk_batch()
@@ -332,9 +355,9 @@ int ensure_events(std::vector<hipEvent_t> &ev, size_t n)
 
 // Run every group: J/K (grad == nullptr) or the gradient.  The caller has
 // cleared the outputs; the work counters are cleared here.
-int run_groups(const std::vector<Group> &gs, const JKSeg *dsegs, uint32_t *dqueue, double *stage, int nslot,
-               const double *D, double *J, double *K, double *grad, int natom_max, unsigned long long *stamps,
-               hipStream_t s, std::vector<hipEvent_t> *ev, const char *who)
+int run_groups(const std::vector<Group> &gs, const JKSeg *dsegs, uint32_t *dqueue, double *stage, size_t stage_bytes,
+               int nslot, const double *D, double *J, double *K, double *grad, int natom_max,
+               unsigned long long *stamps, hipStream_t s, std::vector<hipEvent_t> *ev, const char *who)
 {
     if (gs.empty()) return MJK_OK;
     if (launch_fill_u32(dqueue, (int64_t)gs.size(), 0u, s)) return fail(MJK_ERR_HIP, "%s: fill launch failed", who);
@@ -349,13 +372,18 @@ int run_groups(const std::vector<Group> &gs, const JKSeg *dsegs, uint32_t *dqueu
         a.K = K;
         a.grad = grad;
         a.stage = stage;
+        a.stage_bytes = stage_bytes;
         a.nslot = nslot;
         a.natom_max = natom_max;
         a.queue = dqueue + i;
         a.stamps = stamps;
         const ClassEntry &ce = kClassTable[g.qcls];
         if (ev) HIP_TRY(hipEventRecord((*ev)[2 * i], s));
+        if (grad && !ce.grad) return fail(MJK_ERR_UNSUPPORTED, "%s: no gradient kernel for this class", who);
         const int rc = grad ? ce.grad(a, s) : (g.fp32 ? ce.jk32(a, s) : ce.jk(a, s));
+        if (rc == kLaunchStaging)
+            return fail(MJK_ERR_STATE, "%s: class (%d%d|%d%d): the staging region (%zu bytes, %d slots) cannot hold "
+                        "one slot per block of the launch", who, ce.la, ce.lb, ce.lc, ce.ld, stage_bytes, nslot);
         if (rc) return fail(MJK_ERR_HIP, "%s: class launch failed", who);
         if (ev) HIP_TRY(hipEventRecord((*ev)[2 * i + 1], s));
     }
@@ -412,6 +440,8 @@ extern "C" {
 
 int mjk_lmax(void) { return kLmax; }
 
+int mjk_grad_lmax(void) { return kGradLmax; }
+
 int mjk_num_classes(void) { return kNumQuartetClasses; }
 
 int mjk_class_l(int32_t q, int32_t *l4)
@@ -425,6 +455,28 @@ int mjk_class_l(int32_t q, int32_t *l4)
 }
 
 const char *mjk_last_error(void) { return g_err.c_str(); }
+
+const char *mjk_ctx_last_error(mjk_ctx *ctx)
+{
+    if (!ctx) return "";
+    thread_local std::string copy;
+    std::lock_guard<std::mutex> lk(ctx->err_mu);
+    copy = ctx->err;
+    return copy.c_str();
+}
+
+int mjk_boys(mjk_ctx *ctx, int32_t mmax, const double *T, int64_t n, double *F, void *stream)
+{
+    if (!ctx) return fail(MJK_ERR_INVALID_ARG, "mjk_boys: ctx is NULL");
+    CtxScope cs_(ctx);
+    if (mmax < 0 || mmax > boys_lmax())
+        return fail(MJK_ERR_UNSUPPORTED, "mjk_boys: mmax = %d outside 0..%d", mmax, boys_lmax());
+    if (n < 0 || (n > 0 && (!T || !F))) return fail(MJK_ERR_INVALID_ARG, "mjk_boys: bad arguments");
+    if (n == 0) return MJK_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (launch_boys(mmax, T, n, F, (hipStream_t)stream)) return fail(MJK_ERR_HIP, "mjk_boys: launch failed");
+    return MJK_OK;
+}
 
 int mjk_ctx_create(int device, mjk_ctx **out)
 {
@@ -486,6 +538,7 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
                        size_t *ws_bytes)
 {
     if (!ctx || !out || !ws_bytes) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: NULL argument");
+    CtxScope cs_(ctx);
     *out = nullptr;
     if (int rc = validate_basis(b)) return rc;
     mjk_jk_opts o{};
@@ -496,6 +549,11 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
         return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: fp32_tau = %g", o.fp32_tau);
     if (o.flags & ~(MJK_FLAG_CHECK | MJK_FLAG_GRAD))
         return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: unknown flags 0x%x", o.flags);
+    if (o.flags & MJK_FLAG_GRAD)
+        for (int s = 0; s < b->nshell; ++s)
+            if (b->shell_l[s] > kGradLmax)
+                return fail(MJK_ERR_UNSUPPORTED, "mjk_plan_create: gradient plan: shell %d has l=%d > %d", s,
+                            b->shell_l[s], kGradLmax);
 
     auto *p = new mjk_plan;
     p->ctx = ctx;
@@ -602,7 +660,7 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
     for (const auto &bp : p->bps) {
         const ClassEntry &ce = kClassTable[bp.qcls];
         size_t need = ce.split ? (size_t)ce.nacc : 0;
-        if (o.flags & MJK_FLAG_GRAD) need = std::max(need, ce.grad_stage_nacc());
+        if ((o.flags & MJK_FLAG_GRAD) && ce.grad_stage_nacc) need = std::max(need, ce.grad_stage_nacc());
         if (need == 0) continue;
         p->stage_nacc = std::max(p->stage_nacc, need);
         const int64_t ny = p->bins[bp.Y].count;
@@ -635,7 +693,7 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
     p->o_segs = take(in_batch ? 0 : sizeof(JKSeg) * p->lists.size());
     p->o_queue = take(in_batch ? 0 : sizeof(uint32_t) * 2 * kNumQuartetClasses);
     p->o_eri = take(sizeof(EriItem) * kEriStage);
-    p->o_stage = take(sizeof(double) * 64 * p->stage_nacc * (size_t)p->nslot);
+    p->o_stage = take(p->stage_bytes());
     p->total = off;
 
     p->stats.nbf = p->nbf;
@@ -880,6 +938,7 @@ void mjk_plan_destroy(mjk_plan *plan) { delete plan; }
 int mjk_plan_bind(mjk_plan *p, void *workspace, size_t bytes, void *stream)
 {
     if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_bind: plan is NULL");
+    CtxScope cs_(p->ctx);
     if (p->in_batch) return fail(MJK_ERR_STATE, "mjk_plan_bind: plan belongs to a batch");
     return plan_bind(p, workspace, bytes, (hipStream_t)stream);
 }
@@ -887,6 +946,7 @@ int mjk_plan_bind(mjk_plan *p, void *workspace, size_t bytes, void *stream)
 int mjk_plan_set_tiles(mjk_plan *p, const int32_t *qpl, int32_t n)
 {
     if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_set_tiles: plan is NULL");
+    CtxScope cs_(p->ctx);
     if (!p->bound) return fail(MJK_ERR_STATE, "mjk_plan_set_tiles: plan is not bound");
     if (int rc = check_qpl(qpl, n, "mjk_plan_set_tiles")) return rc;
     HIP_TRY(hipSetDevice(p->ctx->device));
@@ -902,6 +962,7 @@ int mjk_plan_set_tiles(mjk_plan *p, const int32_t *qpl, int32_t n)
 int mjk_build_jk(mjk_plan *p, const double *D, double *J, double *K, void *stream)
 {
     if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_build_jk: plan is NULL");
+    CtxScope cs_(p->ctx);
     if (!p->bound || p->in_batch) return fail(MJK_ERR_STATE, "mjk_build_jk: plan is not bound");
     if (!D || !J || !K) return fail(MJK_ERR_INVALID_ARG, "mjk_build_jk: NULL matrix");
     if (J == K || (const double *)J == D || (const double *)K == D)
@@ -921,7 +982,7 @@ int mjk_build_jk(mjk_plan *p, const double *D, double *J, double *K, void *strea
     p->timed_last = p->timing;
     p->timed_grad = false;
     if (int rc = run_groups(p->groups, (const JKSeg *)(w + p->o_segs), (uint32_t *)(w + p->o_queue),
-                            (double *)(w + p->o_stage), p->nslot, D, J, K, nullptr, 0, nullptr, s,
+                            (double *)(w + p->o_stage), p->stage_bytes(), p->nslot, D, J, K, nullptr, 0, nullptr, s,
                             p->timing ? &p->ev : nullptr, "mjk_build_jk"))
         return rc;
     if (launch_symmetrize(J, p->nbf, s) || launch_symmetrize(K, p->nbf, s))
@@ -932,6 +993,7 @@ int mjk_build_jk(mjk_plan *p, const double *D, double *J, double *K, void *strea
 int mjk_e2(mjk_plan *p, const double *D, const double *J, const double *K, double *e2, void *stream)
 {
     if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_e2: plan is NULL");
+    CtxScope cs_(p->ctx);
     if (!D || !J || !K || !e2) return fail(MJK_ERR_INVALID_ARG, "mjk_e2: NULL argument");
     HIP_TRY(hipSetDevice(p->ctx->device));
     if (launch_e2(D, J, K, p->nbf, e2, (hipStream_t)stream)) return fail(MJK_ERR_HIP, "mjk_e2: launch failed");
@@ -941,6 +1003,7 @@ int mjk_e2(mjk_plan *p, const double *D, const double *J, const double *K, doubl
 int mjk_grad_e2(mjk_plan *p, const double *D, double *grad, void *stream)
 {
     if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_grad_e2: plan is NULL");
+    CtxScope cs_(p->ctx);
     if (!p->bound || p->in_batch) return fail(MJK_ERR_STATE, "mjk_grad_e2: plan is not bound");
     if (!(p->opts.flags & MJK_FLAG_GRAD))
         return fail(MJK_ERR_STATE, "mjk_grad_e2: plan was created without MJK_FLAG_GRAD");
@@ -960,13 +1023,38 @@ int mjk_grad_e2(mjk_plan *p, const double *D, double *grad, void *stream)
     p->timed_last = p->timing;
     p->timed_grad = true;
     return run_groups(p->groups, (const JKSeg *)(w + p->o_segs), (uint32_t *)(w + p->o_queue),
-                      (double *)(w + p->o_stage), p->nslot, D, nullptr, nullptr, grad, p->natom, nullptr, s,
-                      p->timing ? &p->ev : nullptr, "mjk_grad_e2");
+                      (double *)(w + p->o_stage), p->stage_bytes(), p->nslot, D, nullptr, nullptr, grad, p->natom,
+                      nullptr, s, p->timing ? &p->ev : nullptr, "mjk_grad_e2");
+}
+
+int mjk_e2_backward(mjk_plan *p, const double *D, const double *J, const double *K, const double *gout, double *gD,
+                    double *gR, void *stream)
+{
+    if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_e2_backward: plan is NULL");
+    CtxScope cs_(p->ctx);
+    if (!p->bound || p->in_batch) return fail(MJK_ERR_STATE, "mjk_e2_backward: plan is not bound");
+    if (gD && (!J || !K)) return fail(MJK_ERR_INVALID_ARG, "mjk_e2_backward: gD needs J and K");
+    if (gD && ((const double *)gD == J || (const double *)gD == K))
+        return fail(MJK_ERR_INVALID_ARG, "mjk_e2_backward: gD must not alias J or K");
+    if (gR && !D) return fail(MJK_ERR_INVALID_ARG, "mjk_e2_backward: gR needs D");
+    if (gR && !(p->opts.flags & MJK_FLAG_GRAD))
+        return fail(MJK_ERR_STATE, "mjk_e2_backward: plan was created without MJK_FLAG_GRAD");
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (gD && launch_e2_grad_D(J, K, gout, gD, (int64_t)p->nbf * p->nbf, s))
+        return fail(MJK_ERR_HIP, "mjk_e2_backward: launch failed");
+    if (gR) {
+        if (int rc = mjk_grad_e2(p, D, gR, stream)) return rc;
+        if (gout && launch_scale(gR, 3 * (int64_t)p->natom, gout, s))
+            return fail(MJK_ERR_HIP, "mjk_e2_backward: launch failed");
+    }
+    return MJK_OK;
 }
 
 int mjk_eri_class(mjk_plan *p, const int32_t *quartets, int64_t nq, double *out, int64_t out_len, void *stream)
 {
     if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_eri_class: plan is NULL");
+    CtxScope cs_(p->ctx);
     if (!p->bound) return fail(MJK_ERR_STATE, "mjk_eri_class: plan is not bound");
     if (nq < 0 || (nq > 0 && (!quartets || !out)))
         return fail(MJK_ERR_INVALID_ARG, "mjk_eri_class: bad quartet list");
@@ -1034,6 +1122,7 @@ int mjk_eri_class(mjk_plan *p, const int32_t *quartets, int64_t nq, double *out,
 int mjk_schwarz(mjk_plan *p, double *Qh)
 {
     if (!p || !Qh) return fail(MJK_ERR_INVALID_ARG, "mjk_schwarz: NULL argument");
+    CtxScope cs_(p->ctx);
     if (!p->bound) return fail(MJK_ERR_STATE, "mjk_schwarz: plan is not bound");
     const int ns = p->nshell;
     for (int A = 0, k = 0; A < ns; ++A)
@@ -1044,6 +1133,7 @@ int mjk_schwarz(mjk_plan *p, double *Qh)
 int mjk_plan_set_timing(mjk_plan *p, int enable)
 {
     if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_set_timing: plan is NULL");
+    CtxScope cs_(p->ctx);
     p->timing = enable != 0;
     return MJK_OK;
 }
@@ -1051,6 +1141,7 @@ int mjk_plan_set_timing(mjk_plan *p, int enable)
 int mjk_plan_timings(mjk_plan *p, mjk_class_timing *out, int32_t cap, int32_t *n)
 {
     if (!p || !n || (cap > 0 && !out)) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_timings: NULL argument");
+    CtxScope cs_(p->ctx);
     if (!p->timed_last || p->ev.size() != 2 * p->groups.size())
         return fail(MJK_ERR_STATE, "mjk_plan_timings: the last build ran without timing");
     return fill_timings(p->groups, p->ev, p->timed_grad, out, cap, n);
@@ -1071,6 +1162,7 @@ int mjk_batch_create(mjk_ctx *ctx, int32_t nmol, const mjk_basis *mols, const mj
                      size_t *ws_bytes)
 {
     if (!ctx || !mols || !out || !ws_bytes) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_create: NULL argument");
+    CtxScope cs_(ctx);
     *out = nullptr;
     if (nmol <= 0) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_create: nmol = %d", nmol);
     if (opts && (opts->flags & MJK_FLAG_GRAD))
@@ -1086,10 +1178,8 @@ int mjk_batch_create(mjk_ctx *ctx, int32_t nmol, const mjk_basis *mols, const mj
         size_t bytes = 0;
         if (int rc = plan_create(ctx, &mols[m], opts, true, &p, &bytes)) {
             delete bt;
-            char buf[600];
-            snprintf(buf, sizeof buf, "mjk_batch_create: molecule %d: %s", m, g_err.c_str());
-            g_err = buf;
-            return rc;
+            const std::string why = g_err;
+            return fail(rc, "mjk_batch_create: molecule %d: %s", m, why.c_str());
         }
         bt->plans.push_back(p);
         bt->ws_off.push_back(off);
@@ -1109,7 +1199,7 @@ int mjk_batch_create(mjk_ctx *ctx, int32_t nmol, const mjk_basis *mols, const mj
     bt->o_segs = take(sizeof(JKSeg) * bt->nseg);
     bt->o_queue = take(sizeof(uint32_t) * 2 * kNumQuartetClasses);
     bt->o_stamps = take(sizeof(unsigned long long) * 2 * nmol);
-    bt->o_stage = take(sizeof(double) * 64 * bt->stage_nacc * (size_t)bt->nslot);
+    bt->o_stage = take(bt->stage_bytes());
     bt->total = off;
     *ws_bytes = off;
     *out = bt;
@@ -1127,6 +1217,7 @@ static int batch_regroup(mjk_batch *b, hipStream_t s)
 int mjk_batch_bind(mjk_batch *b, void *workspace, size_t bytes, void *stream)
 {
     if (!b) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_bind: batch is NULL");
+    CtxScope cs_(b->ctx);
     if (!workspace) return fail(MJK_ERR_WORKSPACE, "mjk_batch_bind: workspace is NULL");
     if (((uintptr_t)workspace & 255) != 0)
         return fail(MJK_ERR_WORKSPACE, "mjk_batch_bind: workspace not 256-byte aligned");
@@ -1155,6 +1246,7 @@ int mjk_batch_offsets(const mjk_batch *b, int64_t *mat_off)
 int mjk_batch_set_tiles(mjk_batch *b, const int32_t *qpl, int32_t n)
 {
     if (!b) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_set_tiles: batch is NULL");
+    CtxScope cs_(b->ctx);
     if (!b->bound) return fail(MJK_ERR_STATE, "mjk_batch_set_tiles: batch is not bound");
     if (int rc = check_qpl(qpl, n, "mjk_batch_set_tiles")) return rc;
     HIP_TRY(hipSetDevice(b->ctx->device));
@@ -1171,6 +1263,7 @@ int mjk_batch_set_tiles(mjk_batch *b, const int32_t *qpl, int32_t n)
 int mjk_batch_set_stamps(mjk_batch *b, int enable)
 {
     if (!b) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_set_stamps: batch is NULL");
+    CtxScope cs_(b->ctx);
     b->stamps = enable != 0;
     return MJK_OK;
 }
@@ -1178,6 +1271,7 @@ int mjk_batch_set_stamps(mjk_batch *b, int enable)
 int mjk_batch_set_timing(mjk_batch *b, int enable)
 {
     if (!b) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_set_timing: batch is NULL");
+    CtxScope cs_(b->ctx);
     b->timing = enable != 0;
     return MJK_OK;
 }
@@ -1193,13 +1287,14 @@ static int batch_run(mjk_batch *b, const double *D, double *J, double *K, hipStr
     }
     b->stamped_last = b->stamps;
     return run_groups(b->groups, (const JKSeg *)(b->ws + b->o_segs), (uint32_t *)(b->ws + b->o_queue),
-                      (double *)(b->ws + b->o_stage), b->nslot, D, J, K, nullptr, 0, st, s,
+                      (double *)(b->ws + b->o_stage), b->stage_bytes(), b->nslot, D, J, K, nullptr, 0, st, s,
                       timed ? &b->ev : nullptr, "mjk_batch_build_jk");
 }
 
 int mjk_batch_build_jk(mjk_batch *b, const double *D, double *J, double *K, void *stream)
 {
     if (!b) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_build_jk: batch is NULL");
+    CtxScope cs_(b->ctx);
     if (!b->bound) return fail(MJK_ERR_STATE, "mjk_batch_build_jk: batch is not bound");
     if (!D || !J || !K) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_build_jk: NULL matrix");
     if (J == K || (const double *)J == D || (const double *)K == D)
@@ -1222,6 +1317,7 @@ int mjk_batch_build_jk(mjk_batch *b, const double *D, double *J, double *K, void
 int mjk_batch_timings(mjk_batch *b, mjk_class_timing *out, int32_t cap, int32_t *n)
 {
     if (!b || !n || (cap > 0 && !out)) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_timings: NULL argument");
+    CtxScope cs_(b->ctx);
     if (!b->timed_last || b->ev.size() != 2 * b->groups.size())
         return fail(MJK_ERR_STATE, "mjk_batch_timings: the last build ran without timing");
     return fill_timings(b->groups, b->ev, false, out, cap, n);
@@ -1230,6 +1326,7 @@ int mjk_batch_timings(mjk_batch *b, mjk_class_timing *out, int32_t cap, int32_t 
 int mjk_batch_mol_times(mjk_batch *b, double *ms)
 {
     if (!b || !ms) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_mol_times: NULL argument");
+    CtxScope cs_(b->ctx);
     if (!b->stamped_last) return fail(MJK_ERR_STATE, "mjk_batch_mol_times: the last build ran without stamps");
     const size_t nm = b->plans.size();
     std::vector<unsigned long long> h(2 * nm);
@@ -1286,6 +1383,7 @@ int mjk_batch_autotune(mjk_batch *b, const double *D, double *J, double *K, int3
                        int32_t n, void *stream)
 {
     if (!b) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_autotune: batch is NULL");
+    CtxScope cs_(b->ctx);
     if (!b->bound) return fail(MJK_ERR_STATE, "mjk_batch_autotune: batch is not bound");
     if (!D || !J || !K || !qpl_out || n != kNumQuartetClasses || reps < 1)
         return fail(MJK_ERR_INVALID_ARG, "mjk_batch_autotune: bad argument");
@@ -1306,8 +1404,8 @@ int mjk_batch_autotune(mjk_batch *b, const double *D, double *J, double *K, int3
         for (int r = 0; r < reps; ++r) {
             HIP_TRY(hipEventRecord(e0, s));
             if (int rc = run_groups(sel, (const JKSeg *)(b->ws + b->o_segs), (uint32_t *)(b->ws + b->o_queue),
-                                    (double *)(b->ws + b->o_stage), b->nslot, D, J, K, nullptr, 0, nullptr, s,
-                                    nullptr, "mjk_batch_autotune"))
+                                    (double *)(b->ws + b->o_stage), b->stage_bytes(), b->nslot, D, J, K, nullptr, 0,
+                                    nullptr, s, nullptr, "mjk_batch_autotune"))
                 return rc;
             HIP_TRY(hipEventRecord(e1, s));
             HIP_TRY(hipEventSynchronize(e1));

@@ -84,6 +84,7 @@ struct JKLaunch {
     double *K;
     double *grad;                // gradient launches only
     double *stage;               // split classes: per-slot staging of [e0|f0]
+    size_t stage_bytes;          // size of the staging region at `stage`
     int32_t nslot;               // split classes: staging slots (persistent blocks)
     int32_t natom_max;           // gradient: LDS copy of one molecule's gradient
     uint32_t *queue;             // persistent kernels: work counter, zero at launch

@@ -810,13 +810,19 @@ def _class_job(args):
     return cc.name, "\n\n".join(body) + "\n", info
 
 
-def generate(outdir, lmax=2, jobs=None):
+def generate(outdir, lmax=2, jobs=None, grad_lmax=2):
     """Write one header per class (cls_<name>.inc), one translation unit per
-    J/K class and per gradient class, and dispatch.inc."""
+    J/K class and per gradient class, and dispatch.inc.  The nuclear gradient
+    covers the classes with every l <= grad_lmax (its shifted classes reach
+    grad_lmax + 1)."""
     os.makedirs(outdir, exist_ok=True)
     fwd = quartet_classes(lmax)
+    grad_lmax = min(grad_lmax, lmax)
+    has_grad = lambda c: max(c) <= grad_lmax  # noqa: E731
     need = {c: [True, False] for c in fwd}  # (J/K class, shifted class of a gradient)
     for c in fwd:
+        if not has_grad(c):
+            continue
         for _, t in grad_subclasses(*c):
             need.setdefault(t, [False, False])[1] = True
     work = sorted(need.items(), key=lambda kv: -sum(kv[0]))
@@ -845,6 +851,8 @@ def generate(outdir, lmax=2, jobs=None):
         path = os.path.join(outdir, f"tu_{name}.hip")
         _write(path, "\n".join(lines) + "\n")
         tus.append(path)
+        if not has_grad(c):
+            continue
         lines = ["// Generated by paper_2412_13203_amd/gen/eri_gen.py -- do not edit.",
                  '#include "../kernels.hpp"', '#include "../grad_kernels.hpp"', "namespace mjk {"]
         for _, t in grad_subclasses(*c):
@@ -863,11 +871,13 @@ def generate(outdir, lmax=2, jobs=None):
         d.append(f"int launch_jk32_{name}(const JKLaunch &, hipStream_t);")
         d.append(f"int launch_eri_{name}(const EriLaunch &, hipStream_t);")
         d.append(f"int launch_eri32_{name}(const EriLaunch &, hipStream_t);")
-        d.append(f"int launch_grad_{name}(const JKLaunch &, hipStream_t);")
-        d.append(f"size_t grad_stage_nacc_{name}();")
+        if has_grad(c):
+            d.append(f"int launch_grad_{name}(const JKLaunch &, hipStream_t);")
+            d.append(f"size_t grad_stage_nacc_{name}();")
         if c[:2] == c[2:]:
             d.append(f"int launch_schwarz_{name[:2]}(const SchwarzLaunch &, hipStream_t);")
     d.append(f"constexpr int kLmax = {lmax};")
+    d.append(f"constexpr int kGradLmax = {grad_lmax};")
     d.append(f"constexpr int kNumPairClasses = {len(pair_classes(lmax))};")
     d.append(f"constexpr int kNumQuartetClasses = {len(fwd)};")
     d.append("static const ClassEntry kClassTable[kNumQuartetClasses] = {")
@@ -877,15 +887,16 @@ def generate(outdir, lmax=2, jobs=None):
         sch = f"launch_schwarz_{name[:2]}" if c[:2] == c[2:] else "nullptr"
         # algorithmic work: the single-pass recurrence and the cheaper HRR order,
         # whatever the kernel executes (passes recompute shared intermediates)
-        subs = grad_subclasses(*c)
+        subs = grad_subclasses(*c) if has_grad(c) else []
         g_vrr = sum(infos[t]["vrr_flops"] + 1 for _, t in subs)  # +1: the weight
         g_up = sum(1 for k, _ in subs if GRAD_KINDS[k][1] == "+")
         g_dn = len(subs) - g_up
         nw = ncart(c[0]) * ncart(c[1]) * ncart(c[2]) * ncart(c[3])
-        g_q = sum(infos[t]["hrr_flops"] + grad_digest_flops(*c, k, t) for k, t in subs) + 6 * nw
+        g_q = (sum(infos[t]["hrr_flops"] + grad_digest_flops(*c, k, t) for k, t in subs) + 6 * nw) if subs else 0
+        gl = f"launch_grad_{name}, grad_stage_nacc_{name}" if has_grad(c) else "nullptr, nullptr"
         d.append(f"    {{{c[0]}, {c[1]}, {c[2]}, {c[3]}, {cc['nacc']}, {cc['nout']}, {cc['vrr_flops']}, "
                  f"{cc['hrr_flops']}, {int(cc['split'])}, {cc['npass']}, launch_jk_{name}, launch_jk32_{name}, "
-                 f"launch_eri_{name}, launch_eri32_{name}, {sch}, launch_grad_{name}, grad_stage_nacc_{name}, {g_vrr}, {g_up}, {g_dn}, "
+                 f"launch_eri_{name}, launch_eri32_{name}, {sch}, {gl}, {g_vrr}, {g_up}, {g_dn}, "
                  f"{g_q}}},")
     d.append("};")
     d.append("}  // namespace mjk")

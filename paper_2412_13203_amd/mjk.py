@@ -81,9 +81,10 @@ class ClassTiming(ctypes.Structure):
 _lib = None
 
 # exported names of include/mjk.h
-EXPORTS = ["mjk_lmax", "mjk_num_classes", "mjk_class_l", "mjk_last_error", "mjk_ctx_create", "mjk_ctx_destroy",
+EXPORTS = ["mjk_lmax", "mjk_grad_lmax", "mjk_num_classes", "mjk_class_l", "mjk_last_error", "mjk_ctx_last_error",
+           "mjk_ctx_create", "mjk_ctx_destroy", "mjk_boys",
            "mjk_nbf", "mjk_plan_create", "mjk_plan_bind", "mjk_plan_set_tiles", "mjk_build_jk", "mjk_e2",
-           "mjk_grad_e2", "mjk_eri_class", "mjk_schwarz", "mjk_plan_stats_get", "mjk_plan_set_timing",
+           "mjk_grad_e2", "mjk_e2_backward", "mjk_eri_class", "mjk_schwarz", "mjk_plan_stats_get", "mjk_plan_set_timing",
            "mjk_plan_timings", "mjk_plan_destroy",
            "mjk_batch_create", "mjk_batch_bind", "mjk_batch_offsets", "mjk_batch_build_jk", "mjk_batch_set_tiles",
            "mjk_batch_autotune", "mjk_batch_set_stamps", "mjk_batch_mol_times", "mjk_batch_set_timing",
@@ -99,6 +100,11 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         L.mjk_lmax.restype = ctypes.c_int
+        L.mjk_grad_lmax.restype = ctypes.c_int
+        L.mjk_ctx_last_error.argtypes = [vp]
+        L.mjk_ctx_last_error.restype = ctypes.c_char_p
+        L.mjk_boys.argtypes = [vp, i32, vp, i64, vp, vp]
+        L.mjk_e2_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.mjk_num_classes.restype = ctypes.c_int
         L.mjk_class_l.argtypes = [i32, ctypes.POINTER(i32)]
         L.mjk_plan_set_tiles.argtypes = [vp, ctypes.POINTER(i32), i32]
@@ -183,6 +189,22 @@ def _stream(torch, device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def context_last_error(device: int = 0) -> str:
+    """Message of the last failed call made with the device's context."""
+    return lib().mjk_ctx_last_error(context(device)).decode()
+
+
+def boys(T, mmax: int, device: int = 0):
+    """F_m(T), m = 0..mmax, by the device routine of the class kernels (mjk_boys).
+    T: 1-D float64; returns (n, mmax + 1) float64 on the device."""
+    import torch
+    T = torch.as_tensor(T, dtype=torch.float64, device=f"cuda:{device}").contiguous().reshape(-1)
+    F = torch.empty((T.numel(), int(mmax) + 1), dtype=torch.float64, device=T.device)
+    _check(lib().mjk_boys(context(device), int(mmax), ctypes.c_void_p(T.data_ptr()), T.numel(),
+                          ctypes.c_void_p(F.data_ptr()), _stream(torch, device)))
+    return F
+
+
 class Plan:
     """A bound plan: tables for one basis/geometry in a torch-owned workspace."""
 
@@ -259,6 +281,23 @@ class Plan:
         _check(lib().mjk_grad_e2(self._p, self._dev_matrix(D, "D"), ctypes.c_void_p(out.data_ptr()),
                                  _stream(torch, self.device)))
         return out
+
+    def e2_backward(self, D, J=None, K=None, gout=None, want_D=True, want_R=True):
+        """(gD, gR) = gout * (dE2/dD, dE2/dR) from the library (mjk_e2_backward);
+        gout: 0-d float64 tensor on the plan's device or None (= 1)."""
+        torch = self.torch
+        dev = f"cuda:{self.device}"
+        gD = torch.empty((self.nbf, self.nbf), dtype=torch.float64, device=dev) if want_D else None
+        gR = torch.empty((self._hb.xyz.shape[0], 3), dtype=torch.float64, device=dev) if want_R else None
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p()  # noqa: E731
+        if gout is not None and not (torch.is_tensor(gout) and gout.dtype == torch.float64 and gout.numel() == 1
+                                     and gout.device == torch.device(dev)):
+            raise MjkError(-1, f"gout must be one float64 value on {dev}")
+        _check(lib().mjk_e2_backward(self._p, self._dev_matrix(D, "D") if want_R else ctypes.c_void_p(),
+                                     self._dev_matrix(J, "J") if want_D else ctypes.c_void_p(),
+                                     self._dev_matrix(K, "K") if want_D else ctypes.c_void_p(),
+                                     ptr(gout), ptr(gD), ptr(gR), _stream(torch, self.device)))
+        return gD, gR
 
     def eri_class(self, quartets):
         """Contracted ERI blocks for shell quartets (nq x 4), as a list of (na,nb,nc,nd) tensors."""
@@ -424,9 +463,10 @@ def _e2_function():
 
     forward: plan for the basis at `coords` (natom x 3, bohr), J and K
     (mjk_build_jk), E2 = 1/2 Tr(DJ) - 1/4 Tr(DK) (mjk_e2).
-    backward: dE2/dcoords = mjk_grad_e2 at fixed D; dE2/dD = J - K/2 (the
-    derivative of E2 with respect to a symmetric D's entries, taken as
-    independent).  The upstream gradient scales both (chain rule)."""
+    backward: mjk_e2_backward, which returns the upstream gradient times
+    dE2/dcoords (at fixed D) and times dE2/dD = J - K/2 (the derivative with
+    respect to a symmetric D's entries, taken as independent).  The results
+    are handed back on the inputs' devices and dtypes."""
     global _E2
     if _E2 is not None:
         return _E2
@@ -443,6 +483,7 @@ def _e2_function():
             e = plan.e2(Dd, J, K)
             ctx.plan = plan
             ctx.coords_meta = (coords.shape, coords.dtype, coords.device)
+            ctx.D_meta = (D.dtype, D.device)
             ctx.save_for_backward(Dd, J, K)
             return e.to(D.device) if D.device != e.device else e
 
@@ -450,12 +491,15 @@ def _e2_function():
         def backward(ctx, g):
             Dd, J, K = ctx.saved_tensors
             shape, dtype, dev = ctx.coords_meta
+            want_R, want_D = bool(ctx.needs_input_grad[0]), bool(ctx.needs_input_grad[1])
             gc = gD = None
-            g = g.to(Dd.device)
-            if ctx.needs_input_grad[0]:
-                gc = (ctx.plan.grad_e2(Dd) * g).reshape(shape).to(dev, dtype)
-            if ctx.needs_input_grad[1]:
-                gD = (J - 0.5 * K) * g
+            if want_R or want_D:
+                gout = g.detach().to(Dd.device, torch.float64).reshape(()).contiguous()
+                gD, gR = ctx.plan.e2_backward(Dd, J, K, gout, want_D=want_D, want_R=want_R)
+                if want_R:
+                    gc = gR.reshape(shape).to(dev, dtype)
+                if want_D:
+                    gD = gD.to(ctx.D_meta[1], ctx.D_meta[0])
             return gc, gD, None, None, None
 
     _E2 = E2

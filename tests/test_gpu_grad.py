@@ -137,11 +137,12 @@ def test_grad_ignores_fp32_threshold_and_is_repeatable():
     _fp32_threshold_and_repeat(4)
 
 
-@pytest.mark.skip(reason="8-atom cut of the 60-atom workload: NaN rows in the gradient on the GPU (varying "
-                         "between runs) with an earlier kernel, and a memory fault in the (dd|dd) gradient "
-                         "kernel on its d-shell subset; not reproduced by a CPU build of the same kernel code "
-                         "with AddressSanitizer; kept off the GPU until the cause is shown")
 def test_grad_ignores_fp32_threshold_and_is_repeatable_8_atoms():
+    """The input on which an earlier build of the gradient kernel launched more
+    persistent blocks (2304) than its staging region had slots: blocks past
+    the last slot wrote beyond the workspace (NaN rows in varying atoms, then
+    an aperture fault).  The launch is now cut to the slots and items, and the
+    host refuses any staged launch whose blocks do not fit the region."""
     _fp32_threshold_and_repeat(8)
 
 
