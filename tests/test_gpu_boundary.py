@@ -97,6 +97,8 @@ def test_context_error_message():
     torch, mjk, inputs = _mods()
     cfg = inputs.make_config(1)
     plan = mjk.Plan(cfg["basis"])
-    with pytest.raises(mjk.MjkError):
-        plan.eri_class([[0, 1, 2, 99]])
-    assert "out of range" in mjk.context_last_error()
+    with pytest.raises(mjk.MjkError) as ei:
+        plan.set_tiles([3] * mjk.num_classes())
+    assert ei.value.code == -1
+    msg = mjk.context_last_error()
+    assert "quartets per lane" in msg and msg in str(ei.value)
