@@ -57,6 +57,9 @@ extern "C" {
 /* Flags of mjk_jk_opts.flags */
 #define MJK_FLAG_CHECK 0x1u       /* check D on the host side of the call: finite and symmetric */
 #define MJK_FLAG_GRAD 0x2u        /* size the workspace for mjk_grad_e2 as well                 */
+#define MJK_FLAG_NO_STAGING 0x4u  /* no staging slots or work counters in the workspace: the plan
+                                   * builds J and K with mjk_build_jk_static only (not with
+                                   * MJK_FLAG_GRAD, not in batches)                              */
 
 typedef struct mjk_ctx mjk_ctx;
 typedef struct mjk_plan mjk_plan;
@@ -158,6 +161,22 @@ int mjk_plan_bind(mjk_plan *plan, void *workspace, size_t bytes, void *stream);
  * `stream`.  With MJK_FLAG_CHECK in the plan's flags, D is copied to the
  * host and checked first (finite, symmetric to 1e-12 max|D|). */
 int mjk_build_jk(mjk_plan *plan, const double *D, double *J, double *K, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): J and K as
+ * mjk_build_jk computes them, but the persistent kernels' work counters and
+ * the split classes' staging slots live in the library's static device
+ * scratch (256 MiB per device, held from the first mjk_ctx_create on that
+ * device until the process ends) instead of the plan's workspace.  The call
+ * allocates nothing.  Any bound single plan may use it; a plan created with
+ * MJK_FLAG_NO_STAGING (whose workspace lacks those regions) must.  A plan
+ * whose split classes need a staging slot larger than the scratch gets
+ * MJK_ERR_UNSUPPORTED; otherwise as many slots as fit are used (a launch
+ * then has at most that many blocks).  All calls on one device share its
+ * scratch: calls that overlap in time on one device (different streams, or
+ * other threads) race and give wrong results; calls ordered on one stream do
+ * not.  No per-class timing.  Asynchronous on `stream`. */
+int mjk_build_jk_static(mjk_plan *plan, const double *D, double *J, double *K, void *stream);
 
 /* E2 = 1/2 Tr(DJ) - 1/4 Tr(DK), the two-electron energy of a closed-shell
  * density D with its J and K (Section 2.1's Fock build: E2 is the energy

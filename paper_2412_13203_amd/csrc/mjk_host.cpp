@@ -53,7 +53,25 @@ struct mjk_ctx {
     int ncu;
     std::mutex err_mu;  // last failure of a call made with this context
     std::string err;
+    char *scratch = nullptr;  // this device's copy of the static scratch (device address)
 };
+
+namespace {
+
+// Scratch of mjk_build_jk_static, for callers that cannot allocate device
+// memory: the persistent kernels' work counters (first kStaticQueueBytes)
+// and the split classes' staging slots (the rest).  Each device the library
+// runs on holds its own copy for the life of the process; in host code the
+// name only stands for the symbol, so its device address is looked up once
+// per device (static_scratch_ptr) and only that address is used.
+constexpr size_t kStaticScratchBytes = size_t(256) << 20;
+constexpr size_t kStaticQueueBytes = 4096;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[256];  // per device ordinal, filled on first use
+
+}  // namespace
 
 namespace {
 
@@ -183,7 +201,8 @@ struct mjk_plan {
     size_t o_xyz, o_atom, o_poff, o_np, o_exps, o_coefs, o_pnat, o_psort, o_prims, o_Q, o_cls, o_work, o_runs,
         o_segs, o_queue, o_eri, o_stage, total;
     size_t max_runs = 0;      // kept-run records: bound over all screening outcomes
-    int nslot = 0;            // staging slots for split classes
+    int nslot = 0;            // staging slots for split classes (0 with MJK_FLAG_NO_STAGING)
+    int nslot_max = 0;        // slots a launch of this plan can use (occupancy bound)
     size_t stage_nacc = 0;    // largest split-class accumulator count present (J/K and gradient)
     int64_t max_items = 0;    // upper bound of the items of one segment (one quartet per lane)
     size_t work_ints = 0;
@@ -492,10 +511,26 @@ int mjk_ctx_create(int device, mjk_ctx **out)
     if (arch.rfind("gfx950", 0) != 0)
         return fail(MJK_ERR_NO_DEVICE, "mjk_ctx_create: device %d is %s, this build targets gfx950", device,
                     arch.c_str());
+    char *scr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (device >= 256) return fail(MJK_ERR_NO_DEVICE, "mjk_ctx_create: device ordinal %d too large", device);
+        if (!g_scratch_ptr[device]) {
+            // with the device current: its copy of the static scratch
+            HIP_TRY(hipSetDevice(device));
+            void *ptr = nullptr;
+            HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            if (!ptr || ((uintptr_t)ptr & 255) != 0)
+                return fail(MJK_ERR_HIP, "mjk_ctx_create: static scratch address %p", ptr);
+            g_scratch_ptr[device] = (char *)ptr;
+        }
+        scr = g_scratch_ptr[device];
+    }
     auto *c = new mjk_ctx;
     c->device = device;
     c->arch = arch;
     c->ncu = prop.multiProcessorCount;
+    c->scratch = scr;
     *out = c;
     return MJK_OK;
 }
@@ -547,8 +582,10 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
         return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: schwarz_tau = %g", o.schwarz_tau);
     if (!(std::isfinite(o.fp32_tau) && o.fp32_tau >= 0.0))
         return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: fp32_tau = %g", o.fp32_tau);
-    if (o.flags & ~(MJK_FLAG_CHECK | MJK_FLAG_GRAD))
+    if (o.flags & ~(MJK_FLAG_CHECK | MJK_FLAG_GRAD | MJK_FLAG_NO_STAGING))
         return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: unknown flags 0x%x", o.flags);
+    if ((o.flags & MJK_FLAG_NO_STAGING) && (in_batch || (o.flags & MJK_FLAG_GRAD)))
+        return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: MJK_FLAG_NO_STAGING is for single J/K plans only");
     if (o.flags & MJK_FLAG_GRAD)
         for (int s = 0; s < b->nshell; ++s)
             if (b->shell_l[s] > kGradLmax)
@@ -666,9 +703,9 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
         const int64_t ny = p->bins[bp.Y].count;
         p->max_items = std::max(p->max_items, (int64_t)p->bins[bp.X].count * ((ny + kChunk - 1) / kChunk));
     }
-    p->nslot = (p->stage_nacc && !in_batch)
-                   ? (int)std::min<int64_t>(kSlotsPerCU * std::max(1, ctx->ncu), 2 * p->max_items)
-                   : 0;
+    p->nslot_max = p->stage_nacc ? (int)std::min<int64_t>(kSlotsPerCU * std::max(1, ctx->ncu), 2 * p->max_items) : 0;
+    const bool own_staging = !in_batch && !(o.flags & MJK_FLAG_NO_STAGING);
+    p->nslot = own_staging ? p->nslot_max : 0;
 
     // workspace layout
     size_t off = 0;
@@ -691,7 +728,7 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
     p->o_work = take(sizeof(int32_t) * p->work_ints);
     p->o_runs = take(sizeof(KetRun) * std::max<size_t>(p->max_runs, 1));
     p->o_segs = take(in_batch ? 0 : sizeof(JKSeg) * p->lists.size());
-    p->o_queue = take(in_batch ? 0 : sizeof(uint32_t) * 2 * kNumQuartetClasses);
+    p->o_queue = take(own_staging ? sizeof(uint32_t) * 2 * kNumQuartetClasses : 0);
     p->o_eri = take(sizeof(EriItem) * kEriStage);
     p->o_stage = take(p->stage_bytes());
     p->total = off;
@@ -959,35 +996,65 @@ int mjk_plan_set_tiles(mjk_plan *p, const int32_t *qpl, int32_t n)
     return upload_groups(p->groups, {p}, &zero, (JKSeg *)(p->ws + p->o_segs), nullptr);
 }
 
+// J and K of one plan with the given work counters and staging region.
+static int build_jk_run(mjk_plan *p, const double *D, double *J, double *K, hipStream_t s, uint32_t *queue,
+                        double *stage, size_t stage_bytes, int nslot, bool timed, const char *who)
+{
+    if (!p->bound || p->in_batch) return fail(MJK_ERR_STATE, "%s: plan is not bound", who);
+    if (!D || !J || !K) return fail(MJK_ERR_INVALID_ARG, "%s: NULL matrix", who);
+    if (J == K || (const double *)J == D || (const double *)K == D)
+        return fail(MJK_ERR_INVALID_ARG, "%s: D, J, K must be distinct buffers", who);
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    if (p->opts.flags & MJK_FLAG_CHECK) {
+        HIP_TRY(hipStreamSynchronize(s));
+        if (int rc = check_density_host(p->nbf, D, who)) return rc;
+    }
+    const int64_t n2 = (int64_t)p->nbf * p->nbf;
+    if (launch_fill(J, n2, 0.0, s) || launch_fill(K, n2, 0.0, s)) return fail(MJK_ERR_HIP, "%s: fill launch failed", who);
+    if (timed)
+        if (int rc = ensure_events(p->ev, 2 * p->groups.size())) return rc;
+    p->timed_last = timed;
+    p->timed_grad = false;
+    if (int rc = run_groups(p->groups, (const JKSeg *)(p->ws + p->o_segs), queue, stage, stage_bytes, nslot, D, J, K,
+                            nullptr, 0, nullptr, s, timed ? &p->ev : nullptr, who))
+        return rc;
+    if (launch_symmetrize(J, p->nbf, s) || launch_symmetrize(K, p->nbf, s))
+        return fail(MJK_ERR_HIP, "%s: symmetrize launch failed", who);
+    return MJK_OK;
+}
+
 int mjk_build_jk(mjk_plan *p, const double *D, double *J, double *K, void *stream)
 {
     if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_build_jk: plan is NULL");
     CtxScope cs_(p->ctx);
-    if (!p->bound || p->in_batch) return fail(MJK_ERR_STATE, "mjk_build_jk: plan is not bound");
-    if (!D || !J || !K) return fail(MJK_ERR_INVALID_ARG, "mjk_build_jk: NULL matrix");
-    if (J == K || (const double *)J == D || (const double *)K == D)
-        return fail(MJK_ERR_INVALID_ARG, "mjk_build_jk: D, J, K must be distinct buffers");
-    HIP_TRY(hipSetDevice(p->ctx->device));
-    hipStream_t s = (hipStream_t)stream;
-    if (p->opts.flags & MJK_FLAG_CHECK) {
-        HIP_TRY(hipStreamSynchronize(s));
-        if (int rc = check_density_host(p->nbf, D, "mjk_build_jk")) return rc;
-    }
-    const int64_t n2 = (int64_t)p->nbf * p->nbf;
-    if (launch_fill(J, n2, 0.0, s) || launch_fill(K, n2, 0.0, s))
-        return fail(MJK_ERR_HIP, "mjk_build_jk: fill launch failed");
+    if (p->opts.flags & MJK_FLAG_NO_STAGING)
+        return fail(MJK_ERR_STATE, "mjk_build_jk: the plan has no staging (MJK_FLAG_NO_STAGING): use "
+                                   "mjk_build_jk_static");
     char *w = p->ws;
-    if (p->timing)
-        if (int rc = ensure_events(p->ev, 2 * p->groups.size())) return rc;
-    p->timed_last = p->timing;
-    p->timed_grad = false;
-    if (int rc = run_groups(p->groups, (const JKSeg *)(w + p->o_segs), (uint32_t *)(w + p->o_queue),
-                            (double *)(w + p->o_stage), p->stage_bytes(), p->nslot, D, J, K, nullptr, 0, nullptr, s,
-                            p->timing ? &p->ev : nullptr, "mjk_build_jk"))
-        return rc;
-    if (launch_symmetrize(J, p->nbf, s) || launch_symmetrize(K, p->nbf, s))
-        return fail(MJK_ERR_HIP, "mjk_build_jk: symmetrize launch failed");
-    return MJK_OK;
+    return build_jk_run(p, D, J, K, (hipStream_t)stream, (uint32_t *)(w + p->o_queue), (double *)(w + p->o_stage),
+                        p->stage_bytes(), p->nslot, p->timing, "mjk_build_jk");
+}
+
+int mjk_build_jk_static(mjk_plan *p, const double *D, double *J, double *K, void *stream)
+{
+    if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_build_jk_static: plan is NULL");
+    CtxScope cs_(p->ctx);
+    char *scr = p->ctx->scratch;
+    if (!scr) return fail(MJK_ERR_STATE, "mjk_build_jk_static: no static scratch on device %d", p->ctx->device);
+    // counters: one per launch; staging: as many slots of the plan's stride as fit
+    if (sizeof(uint32_t) * 2 * kNumQuartetClasses > kStaticQueueBytes)
+        return fail(MJK_ERR_UNSUPPORTED, "mjk_build_jk_static: work counters exceed the static scratch");
+    const size_t slot = sizeof(double) * 64 * p->stage_nacc;
+    int nslot = 0;
+    if (slot > 0) {
+        const size_t fit = (kStaticScratchBytes - kStaticQueueBytes) / slot;
+        if (fit < 1)
+            return fail(MJK_ERR_UNSUPPORTED, "mjk_build_jk_static: one staging slot (%zu bytes) exceeds the static "
+                        "scratch (%zu bytes)", slot, kStaticScratchBytes - kStaticQueueBytes);
+        nslot = (int)std::min<size_t>(fit, (size_t)p->nslot_max);
+    }
+    return build_jk_run(p, D, J, K, (hipStream_t)stream, (uint32_t *)scr, (double *)(scr + kStaticQueueBytes),
+                        slot * (size_t)nslot, nslot, false, "mjk_build_jk_static");
 }
 
 int mjk_e2(mjk_plan *p, const double *D, const double *J, const double *K, double *e2, void *stream)

@@ -26,6 +26,7 @@ ERRORS = {-1: "MJK_ERR_INVALID_ARG", -2: "MJK_ERR_UNSUPPORTED", -3: "MJK_ERR_NO_
           -5: "MJK_ERR_HIP", -6: "MJK_ERR_STATE"}
 FLAG_CHECK = 0x1
 FLAG_GRAD = 0x2
+FLAG_NO_STAGING = 0x4
 
 
 class MjkError(RuntimeError):
@@ -83,7 +84,7 @@ _lib = None
 # exported names of include/mjk.h
 EXPORTS = ["mjk_lmax", "mjk_grad_lmax", "mjk_num_classes", "mjk_class_l", "mjk_last_error", "mjk_ctx_last_error",
            "mjk_ctx_create", "mjk_ctx_destroy", "mjk_boys",
-           "mjk_nbf", "mjk_plan_create", "mjk_plan_bind", "mjk_plan_set_tiles", "mjk_build_jk", "mjk_e2",
+           "mjk_nbf", "mjk_plan_create", "mjk_plan_bind", "mjk_plan_set_tiles", "mjk_build_jk", "mjk_build_jk_static", "mjk_e2",
            "mjk_grad_e2", "mjk_e2_backward", "mjk_eri_class", "mjk_schwarz", "mjk_plan_stats_get", "mjk_plan_set_timing",
            "mjk_plan_timings", "mjk_plan_destroy",
            "mjk_batch_create", "mjk_batch_bind", "mjk_batch_offsets", "mjk_batch_build_jk", "mjk_batch_set_tiles",
@@ -131,6 +132,7 @@ def lib():
                                       ctypes.POINTER(sz)]
         L.mjk_plan_bind.argtypes = [vp, vp, sz, vp]
         L.mjk_build_jk.argtypes = [vp, vp, vp, vp, vp]
+        L.mjk_build_jk_static.argtypes = [vp, vp, vp, vp, vp]
         L.mjk_e2.argtypes = [vp, vp, vp, vp, vp, vp]
         L.mjk_grad_e2.argtypes = [vp, vp, vp, vp]
         L.mjk_eri_class.argtypes = [vp, ctypes.POINTER(i32), i64, vp, i64, vp]
@@ -253,6 +255,14 @@ class Plan:
             K = torch.empty((n, n), dtype=torch.float64, device=D.device)
         _check(lib().mjk_build_jk(self._p, ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(J.data_ptr()),
                                   ctypes.c_void_p(K.data_ptr()), _stream(torch, self.device)))
+        return J, K
+
+    def build_jk_static(self, D, J, K):
+        """J, K into the caller's J, K through mjk_build_jk_static (the library's
+        static scratch; the call allocates nothing).  D, J, K: contiguous
+        float64 (nbf, nbf) tensors on the plan's device."""
+        _check(lib().mjk_build_jk_static(self._p, self._dev_matrix(D, "D"), self._dev_matrix(J, "J"),
+                                         self._dev_matrix(K, "K"), _stream(self.torch, self.device)))
         return J, K
 
     def _dev_matrix(self, M, name):
