@@ -200,6 +200,28 @@ def overlap_block(basis: dict, A: int, B: int) -> np.ndarray:
     return out
 
 
+def one_electron(basis: dict, Z) -> tuple:
+    """Whole one-electron matrices (S, T, V), each N x N: overlap, kinetic
+    energy -1/2 nabla^2 and attraction to point nuclei of charge Z[atom] at
+    the atom centres.  With J and K they make the Fock matrix of the SCF loop
+    (Section 2.1)."""
+    h = _BasisHandle(basis)
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    if Z.shape != (h.xyz.shape[0],):
+        raise ValueError("one charge per atom")
+    N = h.nbf
+    S, T, V = np.zeros((N, N)), np.zeros((N, N)), np.zeros((N, N))
+    _check(_load().orc_one_electron(h.ref, _dptr(Z), _dptr(S), _dptr(T), _dptr(V)), "one_electron")
+    return S, T, V
+
+
+def nuclear_repulsion(xyz, Z) -> float:
+    """sum_{A<B} Z_A Z_B / |R_A - R_B|."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    return float(_load().orc_nuclear_repulsion(ctypes.c_int(xyz.shape[0]), _dptr(xyz), _dptr(Z)))
+
+
 def e2(J: np.ndarray, K: np.ndarray, D: np.ndarray) -> float:
     """E2 = 1/2 Tr(DJ) - 1/4 Tr(DK)."""
     return float(0.5 * np.sum(D * J) - 0.25 * np.sum(D * K))
@@ -218,6 +240,7 @@ def _setup_signatures():
     lib = _load()
     lib.orc_boys.restype = ctypes.c_int
     lib.orc_nthreads.restype = ctypes.c_int
+    lib.orc_nuclear_repulsion.restype = ctypes.c_double
 
 
 _setup_signatures()

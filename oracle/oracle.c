@@ -37,7 +37,8 @@
 #include <omp.h>
 #endif
 
-#define ORC_LMAX 4             /* l <= 3 plus one for derivatives   */
+#define ORC_LSHELL 3           /* shells: l <= 3                     */
+#define ORC_LMAX 5             /* l <= 3 plus two (kinetic operator)  */
 #define ORC_EDIM (ORC_LMAX + 1)
 #define ORC_TDIM (2 * ORC_LMAX + 1)
 #define ORC_RDIM (4 * ORC_LMAX + 1)
@@ -97,7 +98,7 @@ static void ao_offsets(const orc_basis *b, int *off)
 static int check_basis(const orc_basis *b)
 {
     for (int s = 0; s < b->nshell; ++s)
-        if (b->shell_l[s] < 0 || b->shell_l[s] > ORC_LMAX - 1 || b->shell_nprim[s] < 1 ||
+        if (b->shell_l[s] < 0 || b->shell_l[s] > ORC_LSHELL || b->shell_nprim[s] < 1 ||
             b->shell_nprim[s] > ORC_MAXPRIM)
             return -2;
     return 0;
@@ -651,6 +652,125 @@ int orc_overlap_block(const orc_basis *B, int SA, int SB, double *out)
 }
 
 /* ------------------------------------------------------------------------ */
+/* One-electron integrals of the SCF loop (Section 2.1: the Fock matrix is   */
+/* the one-electron Hamiltonian plus the two-electron part)                  */
+/* ------------------------------------------------------------------------ */
+
+/* Contracted blocks of shells (SA, SB), na*nb row-major each:
+ *   S_ab = <a|b>,
+ *   T_ab = <a| -1/2 nabla^2 |b>,
+ *   V_ab = sum_C -Z_C <a| 1/|r - R_C| |b>   (point nuclei at the atom centres).
+ * McMurchie-Davidson: with the 1-D Hermite coefficients E^{ij}_t of each
+ * primitive pair and s = sqrt(pi/p) per axis,
+ *   overlap factor   S^x_{ij} = E^{ij}_0 s,
+ *   kinetic factor   K^x_{ij} = -1/2 [ j(j-1) S^x_{i,j-2} - 2 beta (2j+1) S^x_{ij}
+ *                                      + 4 beta^2 S^x_{i,j+2} ]
+ *                    (the second derivative of (x-B)^j exp(-beta (x-B)^2)),
+ *   T = K^x S^y S^z + S^x K^y S^z + S^x S^y K^z,
+ *   V = -Z_C 2 pi / p sum_{tuv} E^x_t E^y_u E^z_v R_{tuv}(p, P - C),
+ * each times exp(-alpha beta / p |AB|^2) and the contraction coefficients. */
+static void one_e_block(const orc_basis *B, const double *Z, int SA, int SB, double *S, double *T, double *V,
+                        prim_pair *pp, herm_R *H)
+{
+    const int la = B->shell_l[SA], lb = B->shell_l[SB];
+    const int na = ncart(la), nb = ncart(lb);
+    const int np = shell_pairs(B, SA, SB, 2, pp);
+    const int nB = B->shell_nprim[SB];
+    memset(S, 0, sizeof(double) * na * nb);
+    memset(T, 0, sizeof(double) * na * nb);
+    memset(V, 0, sizeof(double) * na * nb);
+    H->L = la + lb;
+    int ea[3], eb[3];
+    for (int k = 0; k < np; ++k) {
+        const double c = B->coefs[B->shell_prim_off[SA] + k / nB] * B->coefs[B->shell_prim_off[SB] + k % nB];
+        const double beta = B->exps[B->shell_prim_off[SB] + k % nB];
+        const prim_pair *q = &pp[k];
+        const double s1 = sqrt((double)PI_L / q->p);
+        for (int a = 0; a < na; ++a) {
+            cart_exp(la, a, ea);
+            for (int b = 0; b < nb; ++b) {
+                cart_exp(lb, b, eb);
+                double sx[3], kx[3];
+                for (int x = 0; x < 3; ++x) {
+                    const int i = ea[x], j = eb[x];
+                    sx[x] = q->E[x][i][j][0] * s1;
+                    double d2 = -2.0 * beta * (2 * j + 1) * sx[x] + 4.0 * beta * beta * q->E[x][i][j + 2][0] * s1;
+                    if (j >= 2) d2 += j * (j - 1) * q->E[x][i][j - 2][0] * s1;
+                    kx[x] = -0.5 * d2;
+                }
+                S[a * nb + b] += c * q->pref * sx[0] * sx[1] * sx[2];
+                T[a * nb + b] += c * q->pref *
+                                 (kx[0] * sx[1] * sx[2] + sx[0] * kx[1] * sx[2] + sx[0] * sx[1] * kx[2]);
+            }
+        }
+        for (int C = 0; C < B->natom; ++C) {
+            if (Z[C] == 0.0) continue;
+            const double PC[3] = {q->P[0] - B->xyz[3 * C], q->P[1] - B->xyz[3 * C + 1], q->P[2] - B->xyz[3 * C + 2]};
+            hermite_R(H, q->p, PC);
+            const double pre = -Z[C] * 2.0 * (double)PI_L / q->p * q->pref * c;
+            for (int a = 0; a < na; ++a) {
+                cart_exp(la, a, ea);
+                for (int b = 0; b < nb; ++b) {
+                    cart_exp(lb, b, eb);
+                    double sum = 0.0;
+                    for (int t = 0; t <= ea[0] + eb[0]; ++t)
+                        for (int u = 0; u <= ea[1] + eb[1]; ++u)
+                            for (int v = 0; v <= ea[2] + eb[2]; ++v)
+                                sum += q->E[0][ea[0]][eb[0]][t] * q->E[1][ea[1]][eb[1]][u] *
+                                       q->E[2][ea[2]][eb[2]][v] * H->R[RIDX(H->L, 0, t, u, v)];
+                    V[a * nb + b] += pre * sum;
+                }
+            }
+        }
+    }
+}
+
+/* Whole N x N matrices S, T, V (row-major), every shell pair (A, B). */
+int orc_one_electron(const orc_basis *B, const double *Z, double *S, double *T, double *V)
+{
+    if (check_basis(B)) return -2;
+    const int ns = B->nshell;
+    int *off = (int *)malloc(sizeof(int) * (ns + 1));
+    ao_offsets(B, off);
+    const size_t N = (size_t)off[ns];
+#pragma omp parallel
+    {
+        work_t w;
+        work_init(&w);
+        double bs[100], bt[100], bv[100];
+#pragma omp for schedule(dynamic)
+        for (int AB = 0; AB < ns * ns; ++AB) {
+            const int SA = AB / ns, SB = AB % ns;
+            one_e_block(B, Z, SA, SB, bs, bt, bv, w.bra, &w.H);
+            const int na = ncart(B->shell_l[SA]), nb = ncart(B->shell_l[SB]);
+            for (int a = 0; a < na; ++a)
+                for (int b = 0; b < nb; ++b) {
+                    const size_t i = (size_t)(off[SA] + a) * N + off[SB] + b;
+                    S[i] = bs[a * nb + b];
+                    T[i] = bt[a * nb + b];
+                    V[i] = bv[a * nb + b];
+                }
+        }
+        work_free(&w);
+    }
+    free(off);
+    return 0;
+}
+
+/* Repulsion of the point nuclei, sum_{A<B} Z_A Z_B / |R_A - R_B|. */
+double orc_nuclear_repulsion(int natom, const double *xyz, const double *Z)
+{
+    double e = 0.0;
+    for (int a = 0; a < natom; ++a)
+        for (int b = 0; b < a; ++b) {
+            const double dx = xyz[3 * a] - xyz[3 * b], dy = xyz[3 * a + 1] - xyz[3 * b + 1],
+                         dz = xyz[3 * a + 2] - xyz[3 * b + 2];
+            e += Z[a] * Z[b] / sqrt(dx * dx + dy * dy + dz * dz);
+        }
+    return e;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Nuclear gradient of E2 at fixed density                                  */
 /* ------------------------------------------------------------------------ */
 
@@ -667,7 +787,7 @@ int orc_grad_e2(const orc_basis *B, const double *D, double *grad)
     const int N = off[ns];
     const int na_ = B->natom;
     for (int s = 0; s < ns; ++s)
-        if (B->shell_l[s] > ORC_LMAX - 1 || B->shell_nprim[s] > ORC_MAXPRIM) {
+        if (B->shell_l[s] > ORC_LSHELL || B->shell_nprim[s] > ORC_MAXPRIM) {
             free(off);
             return -2;
         }

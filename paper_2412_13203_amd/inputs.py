@@ -181,7 +181,20 @@ def make_config(i: int, seed: int | None = None, natom: int | None = None) -> di
     scale = 0.3 if cfg["scale"] == "0.3" else 1.0 / math.sqrt(n)
     D = density(rng, n, ncol, scale)
     return {"basis": basis, "D": D, "tau": cfg["tau"], "fp32_tau": cfg["fp32_tau"],
-            "name": f"config{i}", "seed": seed, "natom": na}
+            "name": f"config{i}", "seed": seed, "natom": na, "ncol": ncol}
+
+
+def scf_system(cfg: dict) -> tuple:
+    """Nuclear charges and occupied orbitals of a workload's SCF problem.
+
+    The workloads define no elements; the reading used here: as many doubly
+    occupied orbitals as the recipe's density has columns, and that many
+    electron pairs shared evenly among the atoms, Z_A = 2 nocc / natom (2 for
+    the 4-atom recipe, 4 for the lattice recipes)."""
+    nocc = int(cfg["ncol"])
+    na = int(cfg["natom"])
+    Z = np.full(na, 2.0 * nocc / na)
+    return Z, nocc
 
 
 def make_batch(nmol: int = 64, seed: int = 4, atom_range=(8, 96), shells=(0, 0, 1, 2, 3)) -> list:
