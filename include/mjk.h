@@ -234,6 +234,33 @@ int mjk_plan_set_tiles(mjk_plan *plan, const int32_t *qpl, int32_t n);
 int mjk_eri_class(mjk_plan *plan, const int32_t *quartets, int64_t nq, double *out, int64_t out_len,
                   void *stream);
 
+/* Density-weighted screening for incremental Fock builds (the paper's
+ * related work limits the integrals recomputed per SCF iteration; J and K are
+ * linear in D, so J(D_n) = J(D_{n-1}) + J(D_n - D_{n-1})).  dD: device
+ * float64 nbf x nbf (the density change), read during the call only.  The
+ * plan's work lists are rebuilt so that, on top of the Schwarz screen, a
+ * unique quartet (AB|CD) is skipped when
+ *     Q_AB Q_CD max(w_A, w_B, w_C, w_D') < schwarz_tau,
+ * with w_X the largest |dD| in the rows of shell X and w_D' the largest w
+ * over the second shells of the kets of C's run (a bound on every D block a
+ * quartet's J and K updates read: each contribution is at most
+ * |(ab|cd)| max |dD| over those blocks).  dD = NULL restores the plain lists.
+ * The screen stays in force for every later mjk_build_jk of the plan.
+ * Synchronizes the device (host rebuild of the lists, then an upload). */
+int mjk_plan_set_density_screen(mjk_plan *plan, const double *dD, void *stream);
+
+/* One-electron matrices of the SCF iteration (Section 2.1: the Fock matrix
+ * is the one-electron Hamiltonian T + V plus the two-electron part J - K/2):
+ *   S_mn = <m|n>,  T_mn = <m| -1/2 nabla^2 |n>,
+ *   V_mn = sum_C -Z_C <m| 1/|r - R_C| |n>  (point charges at the atom centres).
+ * S, T, V: device float64 nbf x nbf row-major, overwritten; each may be NULL
+ * (skipped); non-null ones must be distinct.  Z: device float64, natom
+ * charges (finite; the call does not read them on the host).  enuc: one
+ * device float64, sum_{A<B} Z_A Z_B / |R_A - R_B|, or NULL.  Needs a bound
+ * single plan (MJK_ERR_STATE otherwise).  Asynchronous on `stream`. */
+int mjk_one_electron(mjk_plan *plan, const double *Z, double *S, double *T, double *V, double *enuc,
+                     void *stream);
+
 /* Schwarz factors Q[A][B] (host float64, nshell x nshell, symmetric) as
  * used by the plan.  Synchronous. */
 int mjk_schwarz(mjk_plan *plan, double *Q_host);

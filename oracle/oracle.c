@@ -757,12 +757,15 @@ int orc_one_electron(const orc_basis *B, const double *Z, double *S, double *T, 
     return 0;
 }
 
-/* Repulsion of the point nuclei, sum_{A<B} Z_A Z_B / |R_A - R_B|. */
+/* Repulsion of the point nuclei, sum_{A<B} Z_A Z_B / |R_A - R_B|; a centre
+ * without charge (Z = 0, a basis-only centre) adds nothing, also where it
+ * coincides with another atom. */
 double orc_nuclear_repulsion(int natom, const double *xyz, const double *Z)
 {
     double e = 0.0;
     for (int a = 0; a < natom; ++a)
         for (int b = 0; b < a; ++b) {
+            if (Z[a] == 0.0 || Z[b] == 0.0) continue;
             const double dx = xyz[3 * a] - xyz[3 * b], dy = xyz[3 * a + 1] - xyz[3 * b + 1],
                          dz = xyz[3 * a + 2] - xyz[3 * b + 2];
             e += Z[a] * Z[b] / sqrt(dx * dx + dy * dy + dz * dz);

@@ -67,7 +67,7 @@ def build(verbose: bool = True, jobs: int | None = None, lmax: int = 2, out: str
     if os.path.isdir(OBJDIR):
         shutil.rmtree(OBJDIR)
     os.makedirs(OBJDIR, exist_ok=True)
-    srcs = [os.path.join(CSRC, "mjk_host.cpp"), os.path.join(CSRC, "device_util.hip")] + sorted(tus)
+    srcs = [os.path.join(CSRC, f) for f in ("mjk_host.cpp", "device_util.hip", "one_electron.hip")] + sorted(tus)
     # heaviest translation units first
     srcs.sort(key=lambda s: -os.path.getsize(s) if "tu_" not in s else -_weight(s))
     jobs = jobs or min(16, os.cpu_count() or 4)

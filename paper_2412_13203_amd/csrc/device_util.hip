@@ -231,6 +231,32 @@ int launch_boys_upto(int mmax, const double *T, int64_t n, double *F, hipStream_
         return -1;
 }
 
+// out[r] = max_c |M[r][c]|, one block per row (n x n row-major)
+__global__ __launch_bounds__(256) void k_rowmax_abs(const double *__restrict__ M, int n, double *__restrict__ out)
+{
+    __shared__ double part[256];
+    const double *row = M + (size_t)blockIdx.x * n;
+    double m = 0.0;
+    for (int c = threadIdx.x; c < n; c += 256) {
+        const double v = fabs(row[c]);
+        m = v == v ? fmax(m, v) : __builtin_huge_val();  // a NaN reads as infinite
+    }
+    part[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] = fmax(part[threadIdx.x], part[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = part[0];
+}
+
+int launch_rowmax_abs(const double *M, int n, double *out, hipStream_t s)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_rowmax_abs, dim3((unsigned)n), dim3(256), 0, s, M, n, out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int boys_lmax() { return MJK_BOYS_LMAX; }
 
 int launch_boys(int mmax, const double *T, int64_t n, double *F, hipStream_t s)

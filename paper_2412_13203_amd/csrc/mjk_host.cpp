@@ -42,6 +42,10 @@ int launch_stamp_init(unsigned long long *x, int n, hipStream_t s);
 int launch_e2_grad_D(const double *J, const double *K, const double *g, double *out, int64_t n, hipStream_t s);
 int launch_scale(double *x, int64_t n, const double *g, hipStream_t s);
 int launch_boys(int mmax, const double *T, int64_t n, double *F, hipStream_t s);
+int launch_rowmax_abs(const double *M, int n, double *out, hipStream_t s);
+int launch_one_electron(const ShellPairD *pairs, const PrimPairD *prims, const int32_t *cls_idx,
+                        const int32_t *cls_off, int lmax, const double *xyz, const double *Z, int natom, int nbf,
+                        double *S, double *T, double *V, double *enuc, hipStream_t s);
 int boys_lmax();
 }  // namespace mjk
 
@@ -195,11 +199,16 @@ struct mjk_plan {
     std::vector<WorkList> lists;         // bin pair x precision, natural order
     std::vector<int32_t> work;           // host copy of the work-list region
     std::vector<std::vector<int32_t>> class_pairs;  // natural indices per pair class
+    std::vector<int32_t> class_off;      // pair class c: device list entries [class_off[c], class_off[c+1])
     int qpl[kNumQuartetClasses];         // quartets per lane, per class
     std::vector<Group> groups;
+    // class-sorted pair table (host copy) and the runs of every bin: bin-relative start, length
+    std::vector<ShellPairD> psort;
+    std::vector<std::vector<std::pair<int, int>>> bin_runs;
+    bool dens_screen = false;            // work lists carry a density-weighted screen
     // workspace layout (byte offsets)
     size_t o_xyz, o_atom, o_poff, o_np, o_exps, o_coefs, o_pnat, o_psort, o_prims, o_Q, o_cls, o_work, o_runs,
-        o_segs, o_queue, o_eri, o_stage, total;
+        o_segs, o_queue, o_eri, o_rowmax, o_stage, total;
     size_t max_runs = 0;      // kept-run records: bound over all screening outcomes
     int nslot = 0;            // staging slots for split classes (0 with MJK_FLAG_NO_STAGING)
     int nslot_max = 0;        // slots a launch of this plan can use (occupancy bound)
@@ -730,6 +739,7 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
     p->o_segs = take(in_batch ? 0 : sizeof(JKSeg) * p->lists.size());
     p->o_queue = take(own_staging ? sizeof(uint32_t) * 2 * kNumQuartetClasses : 0);
     p->o_eri = take(sizeof(EriItem) * kEriStage);
+    p->o_rowmax = take(sizeof(double) * p->nbf);
     p->o_stage = take(p->stage_bytes());
     p->total = off;
 
@@ -745,91 +755,20 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
 }
 
 // tables, Schwarz factors, sort and work lists of one plan (its workspace)
-static int plan_bind(mjk_plan *p, void *workspace, size_t bytes, hipStream_t s)
+// Stage 2 of the plan: per bin pair, per bra, the kept prefix of every run of
+// the ket bin as kept-run records, the work lists' chunking, the launch groups
+// and their segments; uploads them (synchronizes s).  shell_w (host, one
+// value per shell, or null): weights of a density-weighted screen, applied on
+// top of the Schwarz screen.
+static int build_lists(mjk_plan *p, const double *shell_w, hipStream_t s)
 {
-    if (!workspace) return fail(MJK_ERR_WORKSPACE, "mjk_plan_bind: workspace is NULL");
-    if (((uintptr_t)workspace & 255) != 0) return fail(MJK_ERR_WORKSPACE, "mjk_plan_bind: workspace not 256-byte aligned");
-    if (bytes < p->total)
-        return fail(MJK_ERR_WORKSPACE, "mjk_plan_bind: workspace %zu bytes < %zu needed", bytes, p->total);
-    HIP_TRY(hipSetDevice(p->ctx->device));
-    p->ws = (char *)workspace;
-    p->bound = false;
-    char *w = p->ws;
-    const int ns = p->nshell;
-    HIP_TRY(hipMemcpyAsync(w + p->o_xyz, p->xyz.data(), sizeof(double) * 3 * p->natom, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w + p->o_atom, p->atom.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w + p->o_poff, p->poff.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w + p->o_np, p->np.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w + p->o_exps, p->exps.data(), sizeof(double) * p->nprim, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w + p->o_coefs, p->coefs.data(), sizeof(double) * p->nprim, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w + p->o_pnat, p->pairs_nat.data(), sizeof(ShellPairD) * p->npair, hipMemcpyHostToDevice,
-                           s));
-    auto *pnat = (const ShellPairD *)(w + p->o_pnat);
-    auto *prims = (PrimPairD *)(w + p->o_prims);
-    auto *dQ = (double *)(w + p->o_Q);
-    if (launch_pair_table(pnat, p->npair, (const double *)(w + p->o_xyz), (const int32_t *)(w + p->o_atom),
-                          (const int32_t *)(w + p->o_poff), (const int32_t *)(w + p->o_np),
-                          (const double *)(w + p->o_exps), (const double *)(w + p->o_coefs), prims,
-                          (int)p->nprim_pair, s))
-        return fail(MJK_ERR_HIP, "mjk_plan_bind: pair-table launch failed");
-    // Schwarz factors per pair class
-    std::vector<int32_t> cls_idx;
-    std::vector<size_t> cls_off(kNumPairClasses + 1, 0);
-    for (int c = 0; c < kNumPairClasses; ++c) {
-        cls_off[c] = cls_idx.size();
-        cls_idx.insert(cls_idx.end(), p->class_pairs[c].begin(), p->class_pairs[c].end());
-    }
-    cls_off[kNumPairClasses] = cls_idx.size();
-    auto *didx = (int32_t *)(w + p->o_cls);
-    HIP_TRY(hipMemcpyAsync(didx, cls_idx.data(), sizeof(int32_t) * cls_idx.size(), hipMemcpyHostToDevice, s));
-    for (int q = 0; q < kNumQuartetClasses; ++q) {
-        const ClassEntry &ce = kClassTable[q];
-        if (!ce.schwarz) continue;
-        const int c = pair_class(ce.la, ce.lb);
-        SchwarzLaunch sl{pnat, prims, didx + cls_off[c], (int32_t)(cls_off[c + 1] - cls_off[c]), dQ};
-        if (ce.schwarz(sl, s)) return fail(MJK_ERR_HIP, "mjk_plan_bind: Schwarz launch failed");
-    }
-    p->Q.resize(p->npair);
-    HIP_TRY(hipMemcpyAsync(p->Q.data(), dQ, sizeof(double) * p->npair, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    for (int k = 0; k < p->npair; ++k) {
-        if (!std::isfinite(p->Q[k])) return fail(MJK_ERR_HIP, "mjk_plan_bind: Schwarz factor %d not finite", k);
-        p->pairs_nat[k].Q = p->Q[k];
-    }
-
-    // sort into bins: (class, K-bucket) ascending, then by first shell (runs),
-    // inside a run Q descending, index ascending
-    p->sorted.resize(p->npair);
-    for (int k = 0; k < p->npair; ++k) p->sorted[k] = k;
-    std::stable_sort(p->sorted.begin(), p->sorted.end(), [&](int x, int y) {
-        const ShellPairD &a = p->pairs_nat[x], &b = p->pairs_nat[y];
-        const int ka = a.cls * kNumKBuckets + kbucket(a.nprim), kb = b.cls * kNumKBuckets + kbucket(b.nprim);
-        if (ka != kb) return ka < kb;
-        if (a.A != b.A) return a.A < b.A;
-        if (a.Q != b.Q) return a.Q > b.Q;
-        return x < y;
-    });
-    std::vector<ShellPairD> psort(p->npair);
-    for (int k = 0; k < p->npair; ++k) psort[k] = p->pairs_nat[p->sorted[k]];
-    HIP_TRY(hipMemcpyAsync(w + p->o_psort, psort.data(), sizeof(ShellPairD) * p->npair, hipMemcpyHostToDevice, s));
-    // runs of every bin: bin-relative start and length
-    std::vector<std::vector<std::pair<int, int>>> bin_runs(p->bins.size());
-    for (size_t y = 0; y < p->bins.size(); ++y) {
-        const Bin &Y = p->bins[y];
-        auto &rs = bin_runs[y];
-        for (int k = 0; k < Y.count; ++k) {
-            if (k == 0 || psort[Y.begin + k].A != psort[Y.begin + k - 1].A)
-                rs.push_back({k, 1});
-            else
-                rs.back().second++;
-        }
-        if ((int)rs.size() != Y.nrun) return fail(MJK_ERR_STATE, "mjk_plan_bind: bin %zu: run count changed since create", y);
-    }
-
     // stage 2: per bin pair, per bra, the kept prefix of every run of the ket
     // bin (Q_AB Q_CD >= schwarz_tau; with coinciding bins also ket <= bra),
     // split into its FP64 part (Q_AB Q_CD >= fp32_tau) and FP32 remainder
     const double tau = p->opts.schwarz_tau, tau32 = p->opts.fp32_tau;
+    const std::vector<ShellPairD> &psort = p->psort;
+    const auto &bin_runs = p->bin_runs;
+    char *w = p->ws;
     p->work.assign(p->work_ints, 0);
     std::vector<KetRun> runs;
     runs.reserve(p->max_runs);
@@ -848,6 +787,19 @@ static int plan_bind(mjk_plan *p, void *workspace, size_t bytes, hipStream_t s)
         return a0;
     };
     std::vector<KetRun> r32;
+    // per run of every bin: max(w_C, max over its kets of w_D)
+    std::vector<std::vector<double>> run_w;
+    if (shell_w) {
+        run_w.resize(p->bins.size());
+        for (size_t y = 0; y < p->bins.size(); ++y) {
+            const Bin &Y = p->bins[y];
+            for (const auto &run : bin_runs[y]) {
+                double m = shell_w[psort[Y.begin + run.first].A];
+                for (int k = 0; k < run.second; ++k) m = std::max(m, shell_w[psort[Y.begin + run.first + k].B]);
+                run_w[y].push_back(m);
+            }
+        }
+    }
     for (size_t il = 0; il < p->lists.size(); il += 2) {
         WorkList &l64 = p->lists[il], &l32 = p->lists[il + 1];
         const BinPair &bp = p->bps[l64.bp];
@@ -866,13 +818,17 @@ static int plan_bind(mjk_plan *p, void *workspace, size_t bytes, hipStream_t s)
             rb64[b] = (int32_t)runs.size();
             rb32[b] = (int32_t)r32.size();
             int n64 = 0, n32 = 0;
-            for (const auto &run : yr) {
+            const double wb = shell_w ? std::max(shell_w[psort[X.begin + b].A], shell_w[psort[X.begin + b].B]) : 0.0;
+            for (size_t ri = 0; ri < yr.size(); ++ri) {
+                const auto &run = yr[ri];
                 int len = run.second;
                 if (bp.X == bp.Y) {
                     if (run.first > b) break;
                     len = std::min(len, b - run.first + 1);
                 }
-                const int keep = kept_len(Y, run.first, len, qb, tau);
+                int keep = kept_len(Y, run.first, len, qb, tau);
+                // density-weighted screen: Q_AB Q_CD max(w_A, w_B, w_C, max_D w_D) >= tau
+                if (shell_w) keep = kept_len(Y, run.first, keep, qb * std::max(wb, run_w[bp.Y][ri]), tau);
                 const int k64 = tau32 > 0.0 ? std::min(keep, kept_len(Y, run.first, keep, qb, tau32)) : keep;
                 if (k64 > 0) {
                     runs.push_back({n64, run.first});
@@ -932,6 +888,95 @@ static int plan_bind(mjk_plan *p, void *workspace, size_t bytes, hipStream_t s)
         if (int rc = upload_groups(p->groups, {p}, &zero, (JKSeg *)(w + p->o_segs), s)) return rc;
         p->stats.nlaunch = (int64_t)p->groups.size() + 4;
     }
+    return MJK_OK;
+}
+
+static int plan_bind(mjk_plan *p, void *workspace, size_t bytes, hipStream_t s)
+{
+    if (!workspace) return fail(MJK_ERR_WORKSPACE, "mjk_plan_bind: workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(MJK_ERR_WORKSPACE, "mjk_plan_bind: workspace not 256-byte aligned");
+    if (bytes < p->total)
+        return fail(MJK_ERR_WORKSPACE, "mjk_plan_bind: workspace %zu bytes < %zu needed", bytes, p->total);
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    p->ws = (char *)workspace;
+    p->bound = false;
+    char *w = p->ws;
+    const int ns = p->nshell;
+    HIP_TRY(hipMemcpyAsync(w + p->o_xyz, p->xyz.data(), sizeof(double) * 3 * p->natom, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w + p->o_atom, p->atom.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w + p->o_poff, p->poff.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w + p->o_np, p->np.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w + p->o_exps, p->exps.data(), sizeof(double) * p->nprim, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w + p->o_coefs, p->coefs.data(), sizeof(double) * p->nprim, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w + p->o_pnat, p->pairs_nat.data(), sizeof(ShellPairD) * p->npair, hipMemcpyHostToDevice,
+                           s));
+    auto *pnat = (const ShellPairD *)(w + p->o_pnat);
+    auto *prims = (PrimPairD *)(w + p->o_prims);
+    auto *dQ = (double *)(w + p->o_Q);
+    if (launch_pair_table(pnat, p->npair, (const double *)(w + p->o_xyz), (const int32_t *)(w + p->o_atom),
+                          (const int32_t *)(w + p->o_poff), (const int32_t *)(w + p->o_np),
+                          (const double *)(w + p->o_exps), (const double *)(w + p->o_coefs), prims,
+                          (int)p->nprim_pair, s))
+        return fail(MJK_ERR_HIP, "mjk_plan_bind: pair-table launch failed");
+    // Schwarz factors per pair class
+    std::vector<int32_t> cls_idx;
+    std::vector<size_t> cls_off(kNumPairClasses + 1, 0);
+    for (int c = 0; c < kNumPairClasses; ++c) {
+        cls_off[c] = cls_idx.size();
+        cls_idx.insert(cls_idx.end(), p->class_pairs[c].begin(), p->class_pairs[c].end());
+    }
+    cls_off[kNumPairClasses] = cls_idx.size();
+    p->class_off.assign(cls_off.begin(), cls_off.end());
+    auto *didx = (int32_t *)(w + p->o_cls);
+    HIP_TRY(hipMemcpyAsync(didx, cls_idx.data(), sizeof(int32_t) * cls_idx.size(), hipMemcpyHostToDevice, s));
+    for (int q = 0; q < kNumQuartetClasses; ++q) {
+        const ClassEntry &ce = kClassTable[q];
+        if (!ce.schwarz) continue;
+        const int c = pair_class(ce.la, ce.lb);
+        SchwarzLaunch sl{pnat, prims, didx + cls_off[c], (int32_t)(cls_off[c + 1] - cls_off[c]), dQ};
+        if (ce.schwarz(sl, s)) return fail(MJK_ERR_HIP, "mjk_plan_bind: Schwarz launch failed");
+    }
+    p->Q.resize(p->npair);
+    HIP_TRY(hipMemcpyAsync(p->Q.data(), dQ, sizeof(double) * p->npair, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < p->npair; ++k) {
+        if (!std::isfinite(p->Q[k])) return fail(MJK_ERR_HIP, "mjk_plan_bind: Schwarz factor %d not finite", k);
+        p->pairs_nat[k].Q = p->Q[k];
+    }
+
+    // sort into bins: (class, K-bucket) ascending, then by first shell (runs),
+    // inside a run Q descending, index ascending
+    p->sorted.resize(p->npair);
+    for (int k = 0; k < p->npair; ++k) p->sorted[k] = k;
+    std::stable_sort(p->sorted.begin(), p->sorted.end(), [&](int x, int y) {
+        const ShellPairD &a = p->pairs_nat[x], &b = p->pairs_nat[y];
+        const int ka = a.cls * kNumKBuckets + kbucket(a.nprim), kb = b.cls * kNumKBuckets + kbucket(b.nprim);
+        if (ka != kb) return ka < kb;
+        if (a.A != b.A) return a.A < b.A;
+        if (a.Q != b.Q) return a.Q > b.Q;
+        return x < y;
+    });
+    std::vector<ShellPairD> &psort = p->psort;
+    psort.resize(p->npair);
+    for (int k = 0; k < p->npair; ++k) psort[k] = p->pairs_nat[p->sorted[k]];
+    HIP_TRY(hipMemcpyAsync(w + p->o_psort, psort.data(), sizeof(ShellPairD) * p->npair, hipMemcpyHostToDevice, s));
+    // runs of every bin: bin-relative start and length
+    auto &bin_runs = p->bin_runs;
+    bin_runs.assign(p->bins.size(), {});
+    for (size_t y = 0; y < p->bins.size(); ++y) {
+        const Bin &Y = p->bins[y];
+        auto &rs = bin_runs[y];
+        for (int k = 0; k < Y.count; ++k) {
+            if (k == 0 || psort[Y.begin + k].A != psort[Y.begin + k - 1].A)
+                rs.push_back({k, 1});
+            else
+                rs.back().second++;
+        }
+        if ((int)rs.size() != Y.nrun) return fail(MJK_ERR_STATE, "mjk_plan_bind: bin %zu: run count changed since create", y);
+    }
+
+    p->dens_screen = false;
+    if (int rc = build_lists(p, nullptr, s)) return rc;
     p->bound = true;
     return MJK_OK;
 }
@@ -1183,6 +1228,56 @@ int mjk_eri_class(mjk_plan *p, const int32_t *quartets, int64_t nq, double *out,
             HIP_TRY(hipStreamSynchronize(s));  // the host vector g is pageable and reused
         }
     }
+    return MJK_OK;
+}
+
+int mjk_plan_set_density_screen(mjk_plan *p, const double *dD, void *stream)
+{
+    if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_set_density_screen: plan is NULL");
+    CtxScope cs_(p->ctx);
+    if (!p->bound || p->in_batch) return fail(MJK_ERR_STATE, "mjk_plan_set_density_screen: plan is not bound");
+    if (!dD && !p->dens_screen) return MJK_OK;
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double> shell_w;
+    if (dD) {
+        // largest |dD| of every AO row, then of every shell's rows
+        std::vector<double> row(p->nbf);
+        if (launch_rowmax_abs(dD, p->nbf, (double *)(p->ws + p->o_rowmax), s))
+            return fail(MJK_ERR_HIP, "mjk_plan_set_density_screen: launch failed");
+        HIP_TRY(hipMemcpyAsync(row.data(), p->ws + p->o_rowmax, sizeof(double) * p->nbf, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        shell_w.assign(p->nshell, 0.0);
+        for (int A = 0; A < p->nshell; ++A)
+            for (int a = 0; a < ncart_h(p->l[A]); ++a) {
+                const double v = row[p->ao[A] + a];
+                if (!std::isfinite(v))
+                    return fail(MJK_ERR_INVALID_ARG, "mjk_plan_set_density_screen: dD has a non-finite entry");
+                shell_w[A] = std::max(shell_w[A], v);
+            }
+    }
+    HIP_TRY(hipDeviceSynchronize());  // no launch of this plan may still read the lists
+    if (int rc = build_lists(p, dD ? shell_w.data() : nullptr, s)) return rc;
+    p->dens_screen = dD != nullptr;
+    return MJK_OK;
+}
+
+int mjk_one_electron(mjk_plan *p, const double *Z, double *S, double *T, double *V, double *enuc, void *stream)
+{
+    if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_one_electron: plan is NULL");
+    CtxScope cs_(p->ctx);
+    if (!p->bound || p->in_batch) return fail(MJK_ERR_STATE, "mjk_one_electron: plan is not bound");
+    if (!Z) return fail(MJK_ERR_INVALID_ARG, "mjk_one_electron: Z is NULL");
+    if (!S && !T && !V && !enuc) return MJK_OK;
+    if ((S && (S == T || S == V)) || (T && T == V))
+        return fail(MJK_ERR_INVALID_ARG, "mjk_one_electron: S, T, V must be distinct");
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    char *w = p->ws;
+    if (launch_one_electron((const ShellPairD *)(w + p->o_pnat), (const PrimPairD *)(w + p->o_prims),
+                            (const int32_t *)(w + p->o_cls), p->class_off.data(), kLmax,
+                            (const double *)(w + p->o_xyz), Z, p->natom, p->nbf, S, T, V, enuc,
+                            (hipStream_t)stream))
+        return fail(MJK_ERR_HIP, "mjk_one_electron: launch failed");
     return MJK_OK;
 }
 

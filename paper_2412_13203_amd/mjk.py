@@ -85,7 +85,8 @@ _lib = None
 EXPORTS = ["mjk_lmax", "mjk_grad_lmax", "mjk_num_classes", "mjk_class_l", "mjk_last_error", "mjk_ctx_last_error",
            "mjk_ctx_create", "mjk_ctx_destroy", "mjk_boys",
            "mjk_nbf", "mjk_plan_create", "mjk_plan_bind", "mjk_plan_set_tiles", "mjk_build_jk", "mjk_build_jk_static", "mjk_e2",
-           "mjk_grad_e2", "mjk_e2_backward", "mjk_eri_class", "mjk_schwarz", "mjk_plan_stats_get", "mjk_plan_set_timing",
+           "mjk_grad_e2", "mjk_e2_backward", "mjk_eri_class", "mjk_schwarz", "mjk_one_electron",
+           "mjk_plan_set_density_screen", "mjk_plan_stats_get", "mjk_plan_set_timing",
            "mjk_plan_timings", "mjk_plan_destroy",
            "mjk_batch_create", "mjk_batch_bind", "mjk_batch_offsets", "mjk_batch_build_jk", "mjk_batch_set_tiles",
            "mjk_batch_autotune", "mjk_batch_set_stamps", "mjk_batch_mol_times", "mjk_batch_set_timing",
@@ -137,6 +138,8 @@ def lib():
         L.mjk_grad_e2.argtypes = [vp, vp, vp, vp]
         L.mjk_eri_class.argtypes = [vp, ctypes.POINTER(i32), i64, vp, i64, vp]
         L.mjk_schwarz.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.mjk_one_electron.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.mjk_plan_set_density_screen.argtypes = [vp, vp, vp]
         L.mjk_plan_stats_get.argtypes = [vp, ctypes.POINTER(PlanStats)]
         L.mjk_plan_set_timing.argtypes = [vp, ctypes.c_int]
         L.mjk_plan_timings.argtypes = [vp, ctypes.POINTER(ClassTiming), i32, ctypes.POINTER(i32)]
@@ -340,6 +343,38 @@ class Plan:
         n = ctypes.c_int32(0)
         _check(lib().mjk_plan_timings(self._p, arr, cap, ctypes.byref(n)))
         return [arr[i].as_dict() for i in range(min(n.value, cap))]
+
+    def set_density_screen(self, dD):
+        """Density-weighted screening by the density change dD (contiguous
+        float64 (nbf, nbf) on the plan's device), or None to restore the plain
+        work lists (mjk_plan_set_density_screen)."""
+        ptr = self._dev_matrix(dD, "dD") if dD is not None else ctypes.c_void_p()
+        _check(lib().mjk_plan_set_density_screen(self._p, ptr, _stream(self.torch, self.device)))
+
+    def kept_quartets(self) -> int:
+        """Unique shell quartets the current work lists run."""
+        st = PlanStats()
+        _check(lib().mjk_plan_stats_get(self._p, ctypes.byref(st)))
+        return int(st.nquartet_kept)
+
+    def one_electron(self, Z):
+        """(S, T, V, E_nuc): overlap, kinetic-energy and nuclear-attraction
+        matrices (nbf, nbf) and the nuclear repulsion (0-d), float64 on the
+        plan's device (mjk_one_electron); Z: one charge per atom."""
+        torch = self.torch
+        dev = f"cuda:{self.device}"
+        natom = self._hb.xyz.shape[0]
+        Z = torch.as_tensor(Z, dtype=torch.float64).reshape(-1).to(dev).contiguous()
+        if Z.numel() != natom:
+            raise MjkError(-1, f"Z has {Z.numel()} values, expected {natom}")
+        if not bool(torch.isfinite(Z).all()):
+            raise MjkError(-1, "Z must be finite")
+        n = self.nbf
+        S, T, V = (torch.empty((n, n), dtype=torch.float64, device=dev) for _ in range(3))
+        enuc = torch.empty((), dtype=torch.float64, device=dev)
+        p = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+        _check(lib().mjk_one_electron(self._p, p(Z), p(S), p(T), p(V), p(enuc), _stream(torch, self.device)))
+        return S, T, V, enuc
 
     def schwarz(self):
         ns = len(self._hb.l)

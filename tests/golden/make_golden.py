@@ -9,8 +9,10 @@ Writes
   tests/golden/grad_small.json: E2 and its nuclear gradient at fixed D
     (oracle, every quartet, no screening) for the 4-atom s,s,p workload, a
     4-atom cut of the 60-atom s,s,p,d workload, and 3 atoms of s,p,d shells
-    with 1-4 primitives and two coincident centres.
-    python tests/golden/make_golden.py [jk] [grad]
+    with 1-4 primitives and two coincident centres;
+  tests/golden/scf_small.json: the converged energy of the oracle's RHF loop
+    on the 4-atom cut of the 40-atom s,s,p,d workload.
+    python tests/golden/make_golden.py [jk] [grad] [scf]
 """
 import json
 import os
@@ -55,6 +57,21 @@ def main_grad():
         json.dump(out, fh, indent=1)
 
 
+def main_scf():
+    from oracle import scf
+    out = {"what": "converged RHF energy of the oracle's loop (tau as the recipe, e_tol 1e-12, err_tol 1e-9)",
+           "cases": {}}
+    cfg = inputs.make_config(2, natom=4)
+    Z, nocc = inputs.scf_system(cfg)
+    r = scf.rhf(cfg["basis"], Z, nocc, tau=cfg["tau"], e_tol=1e-12, err_tol=1e-9)
+    assert r["converged"]
+    out["cases"]["config2_4atoms"] = {"energy": r["energy"], "iterations": r["iterations"], "nocc": nocc,
+                                      "Z": [float(z) for z in Z]}
+    print("config2_4atoms", r["energy"], r["iterations"], flush=True)
+    with open(os.path.join(HERE, "scf_small.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+
+
 def main():
     cfg = inputs.make_config(2)
     b, D = cfg["basis"], cfg["D"]
@@ -73,8 +90,10 @@ def main():
 
 
 if __name__ == "__main__":
-    what = sys.argv[1:] or ["jk", "grad"]
+    what = sys.argv[1:] or ["jk", "grad", "scf"]
     if "jk" in what:
         main()
     if "grad" in what:
         main_grad()
+    if "scf" in what:
+        main_scf()

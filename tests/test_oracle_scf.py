@@ -158,6 +158,9 @@ def test_nuclear_repulsion():
     Z = np.array([1.0, 2.0, 3.0])
     ref = 1 * 2 / 2.0 + 1 * 3 / 1.5 + 2 * 3 / 2.5
     assert abs(oracle.nuclear_repulsion(xyz, Z) - ref) < 1e-15
+    # a centre without charge adds nothing, even on top of an atom
+    xyz4 = np.vstack([xyz, xyz[1]])
+    assert abs(oracle.nuclear_repulsion(xyz4, np.append(Z, 0.0)) - ref) < 1e-15
 
 
 @pytest.mark.parametrize("alpha", [0.4, 0.7679, 1.9])
