@@ -17,7 +17,9 @@ times the plain FP64 CPU oracle on a bounded sample of the same workload.
 E2 difference).  `grad`: the 60-atom workload's forward (J/K + E2) and
 backward (nuclear gradient) times.  `batch`: 64 molecules of 8-32 atoms
 (K ~ U{1..6}) built one molecule at a time and as one batch with autotuned
-tiles; per-molecule times come from in-kernel wall-clock stamps.
+tiles; per-molecule times come from in-kernel wall-clock stamps.  `scf`:
+RHF on the 40-atom workload around the library, per-iteration time and the
+J/K share, with full and with incremental (density-screened) Fock builds.
 """
 import argparse
 import json
@@ -48,6 +50,18 @@ def kernel_source_hash(cls):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def kernel_name(cls):
+    """Kernel template that runs J/K class `cls` ("dddp"): the per-lane k_jk or,
+    for classes split into recurrence passes, k_jk_split."""
+    try:
+        recs = json.load(open(os.path.join(ROOT, "paper_2412_13203_amd", "csrc", "gen", "opcount.json")))
+        split = {"".join("spdf"[l] for l in r["tuple"]): r["split"] for r in recs}[cls]
+    except (OSError, KeyError, ValueError):
+        return f"class {cls}"
+    ls = ",".join(str("spdf".index(c)) for c in cls)
+    return f"k_jk_split<{ls}>" if split else f"k_jk<{ls}>"
 
 
 def measured_traffic(cls):
@@ -194,6 +208,39 @@ def grad_comparison(torch, mjk, inputs, dev, steps=2, warmup=1):
     }
 
 
+def scf_comparison(torch, inputs, dev, config=2, natom=None):
+    """The SCF iteration around the library (Section 2.1): RHF on a lattice
+    workload (charges and occupied orbitals from the recipe's density width),
+    once with a full J/K build every iteration and once incremental (density
+    changes with density-weighted screening, a full rebuild every 8
+    iterations and to confirm convergence).  Per-iteration time and the J/K
+    build's share of it, HIP events on the launch stream."""
+    from paper_2412_13203_amd import scf
+    cfg = inputs.make_config(config, natom=natom) if natom else inputs.make_config(config)
+    Z, nocc = inputs.scf_system(cfg)
+    out = {"workload": f"{cfg['natom']}-atom jittered-lattice molecule, s,s,p,d x 3 primitives, nbf {cfg['basis']['nbf']}, "
+                       f"Schwarz {cfg['tau']}, Z = {Z[0]:g} per atom, {nocc} doubly occupied orbitals, RHF + DIIS",
+           "nbf": cfg["basis"]["nbf"]}
+    for mode in ("full", "incremental"):
+        t0 = time.time()
+        r = scf.RHF(cfg["basis"], Z, nocc, tau=cfg["tau"], device=dev)
+        setup = time.time() - t0
+        res = r.run(e_tol=1e-9, err_tol=1e-7, incremental=mode == "incremental",
+                    log=lambda m: print(f"bench: SCF {mode}: {m}", file=sys.stderr, flush=True))
+        it_ms = float(np.sum(res["ms_per_iter"]))
+        jk_ms = float(np.sum(res["ms_jk"]))
+        print(f"bench: SCF {mode}: {res['iterations']} iterations, E = {res['energy']:.10f}, "
+              f"{it_ms / res['iterations']:.1f} ms/iteration, J/K share {jk_ms / it_ms:.3f}", file=sys.stderr,
+              flush=True)
+        out[mode] = {"converged": res["converged"], "iterations": res["iterations"], "energy": res["energy"],
+                     "setup_s": setup, "ms_per_iteration": it_ms / res["iterations"],
+                     "jk_ms_per_iteration": jk_ms / res["iterations"], "jk_share": jk_ms / it_ms,
+                     "total_s": it_ms * 1e-3, "kept_quartets": res["kept_quartets"]}
+    out["incremental_speedup"] = out["full"]["total_s"] / out["incremental"]["total_s"]
+    out["energy_difference"] = abs(out["full"]["energy"] - out["incremental"]["energy"])
+    return out
+
+
 def batch_comparison(torch, mjk, inputs, dev, nmol=64, atom_range=(8, 32), steps=2, tune_reps=2):
     """Many molecules of uneven size: sequential single-molecule FP64 builds
     (default tiles) vs one batch (one launch per class over all molecules),
@@ -298,6 +345,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=2, help="timed builds per batch measurement")
     ap.add_argument("--batch-tune-reps", type=int, default=2,
                     help="builds per autotuner trial (0: no autotuning, default tiles only)")
+    ap.add_argument("--no-scf", action="store_true",
+                    help="skip the SCF driver timing (RHF on the 40-atom workload, full and incremental)")
+    ap.add_argument("--scf-config", type=int, default=2, help="workload of the SCF timing (2: 40 atoms, 3: 120)")
     ap.add_argument("--fp32-tau", type=float, nargs="+", default=[1e-4, 1e-6],
                     help="mixed-precision thresholds for --mixed (first one is the headline)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -416,7 +466,7 @@ def main():
         "cart_eris_per_s": st["ncart_eri_kept"] / (ms_per_step * 1e-3),
         "algorithmic_tflops": total_flops / (ms_per_step * 1e-3) / 1e12,
         "fp64_frac_whole_step": total_flops / (ms_per_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-        "roofline": {"bound": "alu", "kernel": f"k_jk<{dom_cls}>", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+        "roofline": {"bound": "alu", "kernel": kernel_name(dom_cls), "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(dom_cls),
                      "avg_launch_ms": avg_ms, "flops_per_launch": flops_per_launch},
         "classes": classes,
@@ -429,6 +479,8 @@ def main():
     if not args.no_batch:
         out["batch"] = batch_comparison(torch, mjk, inputs, dev, atom_range=tuple(args.batch_atoms),
                                         steps=args.batch_steps, tune_reps=args.batch_tune_reps)
+    if not args.no_scf:
+        out["scf"] = scf_comparison(torch, inputs, dev, config=args.scf_config)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)

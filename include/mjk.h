@@ -240,14 +240,14 @@ int mjk_eri_class(mjk_plan *plan, const int32_t *quartets, int64_t nq, double *o
  * float64 nbf x nbf (the density change), read during the call only.  The
  * plan's work lists are rebuilt so that, on top of the Schwarz screen, a
  * unique quartet (AB|CD) is skipped when
- *     Q_AB Q_CD max(w_A, w_B, w_C, w_D') < schwarz_tau,
+ *     Q_AB Q_CD max(w_A, w_B, w_C, w_D') < tau   (tau >= 0, finite),
  * with w_X the largest |dD| in the rows of shell X and w_D' the largest w
  * over the second shells of the kets of C's run (a bound on every D block a
  * quartet's J and K updates read: each contribution is at most
  * |(ab|cd)| max |dD| over those blocks).  dD = NULL restores the plain lists.
  * The screen stays in force for every later mjk_build_jk of the plan.
  * Synchronizes the device (host rebuild of the lists, then an upload). */
-int mjk_plan_set_density_screen(mjk_plan *plan, const double *dD, void *stream);
+int mjk_plan_set_density_screen(mjk_plan *plan, const double *dD, double tau, void *stream);
 
 /* One-electron matrices of the SCF iteration (Section 2.1: the Fock matrix
  * is the one-electron Hamiltonian T + V plus the two-electron part J - K/2):

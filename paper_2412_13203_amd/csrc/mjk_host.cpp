@@ -758,9 +758,9 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
 // Stage 2 of the plan: per bin pair, per bra, the kept prefix of every run of
 // the ket bin as kept-run records, the work lists' chunking, the launch groups
 // and their segments; uploads them (synchronizes s).  shell_w (host, one
-// value per shell, or null): weights of a density-weighted screen, applied on
-// top of the Schwarz screen.
-static int build_lists(mjk_plan *p, const double *shell_w, hipStream_t s)
+// value per shell, or null): weights of a density-weighted screen with
+// threshold tau_w, applied on top of the Schwarz screen.
+static int build_lists(mjk_plan *p, const double *shell_w, double tau_w, hipStream_t s)
 {
     // stage 2: per bin pair, per bra, the kept prefix of every run of the ket
     // bin (Q_AB Q_CD >= schwarz_tau; with coinciding bins also ket <= bra),
@@ -827,8 +827,8 @@ static int build_lists(mjk_plan *p, const double *shell_w, hipStream_t s)
                     len = std::min(len, b - run.first + 1);
                 }
                 int keep = kept_len(Y, run.first, len, qb, tau);
-                // density-weighted screen: Q_AB Q_CD max(w_A, w_B, w_C, max_D w_D) >= tau
-                if (shell_w) keep = kept_len(Y, run.first, keep, qb * std::max(wb, run_w[bp.Y][ri]), tau);
+                // density-weighted screen: Q_AB Q_CD max(w_A, w_B, w_C, max_D w_D) >= tau_w
+                if (shell_w) keep = kept_len(Y, run.first, keep, qb * std::max(wb, run_w[bp.Y][ri]), tau_w);
                 const int k64 = tau32 > 0.0 ? std::min(keep, kept_len(Y, run.first, keep, qb, tau32)) : keep;
                 if (k64 > 0) {
                     runs.push_back({n64, run.first});
@@ -976,7 +976,7 @@ static int plan_bind(mjk_plan *p, void *workspace, size_t bytes, hipStream_t s)
     }
 
     p->dens_screen = false;
-    if (int rc = build_lists(p, nullptr, s)) return rc;
+    if (int rc = build_lists(p, nullptr, 0.0, s)) return rc;
     p->bound = true;
     return MJK_OK;
 }
@@ -1231,11 +1231,13 @@ int mjk_eri_class(mjk_plan *p, const int32_t *quartets, int64_t nq, double *out,
     return MJK_OK;
 }
 
-int mjk_plan_set_density_screen(mjk_plan *p, const double *dD, void *stream)
+int mjk_plan_set_density_screen(mjk_plan *p, const double *dD, double tau, void *stream)
 {
     if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_set_density_screen: plan is NULL");
     CtxScope cs_(p->ctx);
     if (!p->bound || p->in_batch) return fail(MJK_ERR_STATE, "mjk_plan_set_density_screen: plan is not bound");
+    if (dD && !(std::isfinite(tau) && tau >= 0.0))
+        return fail(MJK_ERR_INVALID_ARG, "mjk_plan_set_density_screen: tau = %g", tau);
     if (!dD && !p->dens_screen) return MJK_OK;
     HIP_TRY(hipSetDevice(p->ctx->device));
     hipStream_t s = (hipStream_t)stream;
@@ -1257,7 +1259,7 @@ int mjk_plan_set_density_screen(mjk_plan *p, const double *dD, void *stream)
             }
     }
     HIP_TRY(hipDeviceSynchronize());  // no launch of this plan may still read the lists
-    if (int rc = build_lists(p, dD ? shell_w.data() : nullptr, s)) return rc;
+    if (int rc = build_lists(p, dD ? shell_w.data() : nullptr, tau, s)) return rc;
     p->dens_screen = dD != nullptr;
     return MJK_OK;
 }

@@ -139,7 +139,7 @@ def lib():
         L.mjk_eri_class.argtypes = [vp, ctypes.POINTER(i32), i64, vp, i64, vp]
         L.mjk_schwarz.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.mjk_one_electron.argtypes = [vp, vp, vp, vp, vp, vp, vp]
-        L.mjk_plan_set_density_screen.argtypes = [vp, vp, vp]
+        L.mjk_plan_set_density_screen.argtypes = [vp, vp, ctypes.c_double, vp]
         L.mjk_plan_stats_get.argtypes = [vp, ctypes.POINTER(PlanStats)]
         L.mjk_plan_set_timing.argtypes = [vp, ctypes.c_int]
         L.mjk_plan_timings.argtypes = [vp, ctypes.POINTER(ClassTiming), i32, ctypes.POINTER(i32)]
@@ -221,6 +221,7 @@ class Plan:
         self.torch = torch
         self.device = device
         self.basis = basis
+        self.tau = float(tau)
         self._hb = _HostBasis(basis)
         ctx = context(device)
         opts = JKOpts(float(tau), float(fp32_tau), int(flags))
@@ -344,12 +345,14 @@ class Plan:
         _check(lib().mjk_plan_timings(self._p, arr, cap, ctypes.byref(n)))
         return [arr[i].as_dict() for i in range(min(n.value, cap))]
 
-    def set_density_screen(self, dD):
+    def set_density_screen(self, dD, tau: float | None = None):
         """Density-weighted screening by the density change dD (contiguous
-        float64 (nbf, nbf) on the plan's device), or None to restore the plain
-        work lists (mjk_plan_set_density_screen)."""
+        float64 (nbf, nbf) on the plan's device) at threshold tau (default:
+        the plan's Schwarz threshold), or dD = None to restore the plain work
+        lists (mjk_plan_set_density_screen)."""
         ptr = self._dev_matrix(dD, "dD") if dD is not None else ctypes.c_void_p()
-        _check(lib().mjk_plan_set_density_screen(self._p, ptr, _stream(self.torch, self.device)))
+        t = self.tau if tau is None else float(tau)
+        _check(lib().mjk_plan_set_density_screen(self._p, ptr, ctypes.c_double(t), _stream(self.torch, self.device)))
 
     def kept_quartets(self) -> int:
         """Unique shell quartets the current work lists run."""

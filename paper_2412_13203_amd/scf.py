@@ -21,11 +21,12 @@ them runs in torch on the same device:
 J(D_n) = J(D_{n-1}) + J(D_n - D_{n-1}) (J and K are linear in D), with the
 screening of each difference build weighted by the difference itself: a
 quartet is skipped when its Schwarz bound times the largest element of the
-difference density in the shell rows it touches is below the plan's
-threshold (`mjk_plan_set_density_screen`).  Every `rebuild_every` iterations
+difference density in the shell rows it touches is below `inc_tau` (default
+the plan's Schwarz threshold / 100; `mjk_plan_set_density_screen`).  Every `rebuild_every` iterations
 (and in the first) the full J and K are rebuilt, which bounds the drift, and
 an iteration that meets the convergence test on an incremental build is
-repeated with a full build of the same density before the loop stops.
+repeated with a full build of the same density before the loop stops (when
+that full build does not confirm it, the rest of the run builds in full).
 """
 from __future__ import annotations
 
@@ -72,7 +73,7 @@ class RHF:
         return 0.5 * (D + D.T), e
 
     def run(self, max_iter: int = 100, e_tol: float = 1e-10, err_tol: float = 1e-8, ndiis: int = 8, D0=None,
-            incremental: bool = False, rebuild_every: int = 8) -> dict:
+            incremental: bool = False, rebuild_every: int = 8, inc_tau: float | None = None, log=None) -> dict:
         torch = self.torch
         stream = torch.cuda.current_stream(self.dev)
         D = self.density(self.H)[0] if D0 is None else torch.as_tensor(D0, dtype=torch.float64, device=self.dev)
@@ -83,17 +84,18 @@ class RHF:
         D_prev = None
         focks, errs = [], []
         energies, t_iter, t_jk, kept, was_full = [], [], [], [], []
-        e_old, converged, it, confirm = None, False, 0, False
+        e_old, converged, it, confirm, inc_off = None, False, 0, False, False
+        inc_tau = self.plan.tau * 1e-2 if inc_tau is None else inc_tau
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         for it in range(1, max_iter + 1):
             ev[0].record(stream)
-            full = not incremental or D_prev is None or confirm or (it - 1) % rebuild_every == 0
+            full = not incremental or inc_off or D_prev is None or confirm or (it - 1) % rebuild_every == 0
             if full:
                 self.plan.set_density_screen(None)
                 self.plan.build_jk(D, J, K)
             else:
                 dD = D - D_prev
-                self.plan.set_density_screen(dD)
+                self.plan.set_density_screen(dD, inc_tau)
                 self.plan.build_jk(dD, dJ, dK)
                 J += dJ
                 K += dK
@@ -108,7 +110,11 @@ class RHF:
             energies.append(e_tot)
             done = e_old is not None and abs(e_tot - e_old) < e_tol and emax < err_tol
             # an incremental build that looks converged is confirmed by a full
-            # build of the same density
+            # build of the same density; if that full build does not confirm
+            # it, the screening noise is at the convergence threshold and the
+            # remaining iterations build J and K in full
+            if confirm and not done:
+                inc_off = True
             confirm = done and not full
             if not done:
                 focks.append(F)
@@ -121,6 +127,9 @@ class RHF:
             ev[2].synchronize()
             t_iter.append(ev[0].elapsed_time(ev[2]))
             t_jk.append(ev[0].elapsed_time(ev[1]))
+            if log is not None:
+                log(f"iteration {it}: E = {e_tot:.10f}, max |FDS - SDF| = {emax:.2e}, "
+                    f"{'full' if full else 'incremental'} J/K {t_jk[-1]:.1f} ms of {t_iter[-1]:.1f} ms")
             e_old = e_tot
             if done and full:
                 converged = True
