@@ -33,7 +33,7 @@ HIP_FLAGS = [
 ]
 
 
-def generate(lmax: int = 2):
+def generate(lmax: int = 3):
     sys.path.insert(0, os.path.join(HERE, "gen"))
     try:
         import boys_gen
@@ -61,7 +61,7 @@ def _compile(src, verbose):
     return obj
 
 
-def build(verbose: bool = True, jobs: int | None = None, lmax: int = 2, out: str | None = None) -> str:
+def build(verbose: bool = True, jobs: int | None = None, lmax: int = 3, out: str | None = None) -> str:
     t0 = time.time()
     tus = generate(lmax)
     if os.path.isdir(OBJDIR):
@@ -95,7 +95,7 @@ def _weight(tu):
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
-    ap.add_argument("--lmax", type=int, default=2)
+    ap.add_argument("--lmax", type=int, default=3)
     ap.add_argument("--out", default=None, help="library path (default: _lib/libmjk.so)")
     args = ap.parse_args()
     build(jobs=args.jobs, lmax=args.lmax, out=args.out)

@@ -11,6 +11,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "mjk_types.hpp"
 #include "stage_guard.hpp"
 
@@ -719,6 +721,8 @@ __device__ __forceinline__ void jk_split_body(const JKLaunch &a)
     // density blocks of one quartet: D_cd, D_ac, D_ad, D_bc, D_bd back to back
     constexpr int OAC = NCD, OAD = OAC + NA * NC, OBC = OAD + NA * ND, OBD = OBC + NB * NC, NDQ = OBD + NB * ND;
     constexpr int KS = (NACC + 63) / 64, KD = (NDQ + 63) / 64;
+    constexpr int KS_PRE = KS <= 16 ? KS : 0;  // staged values prefetched per lane
+    constexpr int KAB = (NAB + 63) / 64;        // bra elements per lane (2 for an (ff| bra)
     constexpr int KAC = (NA * NC + 63) / 64, KBC = (NB * NC + 63) / 64;
     __shared__ double s_buf[NBUF];     // [e][f], then (ab|cd) as [ab][cd]
     __shared__ double s_abf[NAB * NF]; // (ab|f] as [ab][f]
@@ -732,9 +736,10 @@ __device__ __forceinline__ void jk_split_body(const JKLaunch &a)
     static_assert(split_off<LA, LB, LC, LD, S::NPASS>() == NACC, "passes must partition the targets");
     const int lane = threadIdx.x;
     double *stage = a.stage + (size_t)blockIdx.x * NACC * 64;
-    int tpos[KS];  // target of staging position lane + 64 k
+    int tpos[KS_PRE > 0 ? KS_PRE : 1];  // target of staging position lane + 64 k
 #pragma unroll
-    for (int k = 0; k < KS; ++k) tpos[k] = lane + 64 * k < NACC ? split_target<LA, LB, LC, LD>(lane + 64 * k) : 0;
+    for (int k = 0; k < KS_PRE; ++k)
+        tpos[k] = lane + 64 * k < NACC ? split_target<LA, LB, LC, LD>(lane + 64 * k) : 0;
 
     for (;;) {
         const int item = next_item(a, lane);
@@ -750,7 +755,9 @@ __device__ __forceinline__ void jk_split_body(const JKLaunch &a)
         double *__restrict__ Jm = a.J + sg.mat_off;
         double *__restrict__ Km = a.K + sg.mat_off;
         for (int t = lane; t < NAB; t += 64) s_Dab[t] = D[(size_t)(bra.ao_a + t / NB) * N + bra.ao_b + t % NB];
-        double jab = 0.0;  // Jt_ab for ab = lane (lane < NAB), summed over the item
+        double jab[KAB];  // Jt_ab for ab = lane + 64 k (< NAB), summed over the item
+#pragma unroll
+        for (int k = 0; k < KAB; ++k) jab[k] = 0.0;
         // Kt_ac and Kt_bc of the current C (element lane + 64 k), summed over
         // consecutive quartets of one run and added when C changes
         double kac[KAC], kbc[KBC];
@@ -801,12 +808,14 @@ __device__ __forceinline__ void jk_split_body(const JKLaunch &a)
 
             // phase 2: the wave works through this round's quartets.  The
             // staged [e0|f0] and the density blocks of quartet q + 1 are
-            // loaded into registers while quartet q is digested.
-            double pst[KS], pdq[KD];
+            // loaded into registers while quartet q is digested (the staged
+            // values only up to KS_PRE per lane; larger classes copy them
+            // from the slot when their quartet starts).
+            double pst[KS_PRE > 0 ? KS_PRE : 1], pdq[KD];
             auto fetch = [&](int q) {
                 const int ao_c = s_ao[q][0], ao_d = s_ao[q][1];
 #pragma unroll
-                for (int k = 0; k < KS; ++k) {
+                for (int k = 0; k < KS_PRE; ++k) {
                     const int t = lane + 64 * k;
                     pst[k] = t < NACC ? stage[(size_t)q * NACC + t] : 0.0;
                 }
@@ -834,9 +843,14 @@ __device__ __forceinline__ void jk_split_body(const JKLaunch &a)
                     if (cur_c >= 0) flush_c();
                     cur_c = ao_c;
                 }
+                if constexpr (KS_PRE == KS) {
 #pragma unroll
-                for (int k = 0; k < KS; ++k)
-                    if (lane + 64 * k < NACC) s_buf[tpos[k]] = pst[k];
+                    for (int k = 0; k < KS; ++k)
+                        if (lane + 64 * k < NACC) s_buf[tpos[k]] = pst[k];
+                } else {
+                    for (int t = lane; t < NACC; t += 64) s_buf[split_target<LA, LB, LC, LD>(t)] =
+                        stage[(size_t)q * NACC + t];
+                }
 #pragma unroll
                 for (int k = 0; k < KD; ++k)
                     if (lane + 64 * k < NDQ) s_Dq[lane + 64 * k] = pdq[k];
@@ -846,16 +860,20 @@ __device__ __forceinline__ void jk_split_body(const JKLaunch &a)
                 __syncthreads();
                 const double CD[3] = {s_CD[q][0], s_CD[q][1], s_CD[q][2]};
                 const double w = s_w[q];
-                for (int r = lane; r < NAB; r += 64) {
-                    double row[NCD];
-                    S::template hrr_ket_row<double>(s_abf + r * NF, CD, row);
-                    double t = 0.0;
 #pragma unroll
-                    for (int cd = 0; cd < NCD; ++cd) {
-                        s_buf[r * NCD + cd] = row[cd];
-                        t += row[cd] * s_Dcd[cd];
+                for (int k = 0; k < KAB; ++k) {
+                    const int r = lane + 64 * k;
+                    if (r < NAB) {
+                        double row[NCD];
+                        S::template hrr_ket_row<double>(s_abf + r * NF, CD, row);
+                        double t = 0.0;
+#pragma unroll
+                        for (int cd = 0; cd < NCD; ++cd) {
+                            s_buf[r * NCD + cd] = row[cd];
+                            t += row[cd] * s_Dcd[cd];
+                        }
+                        jab[k] += 2.0 * w * t;
                     }
-                    jab += 2.0 * w * t;
                 }
                 __syncthreads();
                 // Jt_cd += 2w sum_ab (ab|cd) D_ab
@@ -921,9 +939,91 @@ __device__ __forceinline__ void jk_split_body(const JKLaunch &a)
             }
         }
         if (cur_c >= 0) flush_c();
-        if (lane < NAB) atomicAdd(Jm + (size_t)(bra.ao_a + lane / NB) * N + bra.ao_b + lane % NB, jab);
+#pragma unroll
+        for (int k = 0; k < KAB; ++k) {
+            const int t = lane + 64 * k;
+            if (t < NAB) atomicAdd(Jm + (size_t)(bra.ao_a + t / NB) * N + bra.ao_b + t % NB, jab[k]);
+        }
         stamp(a, sg.mol, lane, true);
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Explicit ERI blocks (and Schwarz factors) of classes split into recurrence
+// passes: persistent blocks take 64 requested quartets at a time; phase 1 as
+// in the split J/K kernel (one quartet per lane, passes into the block's
+// staging slot), phase 2 one quartet at a time: bra HRR one ket column per
+// lane, ket HRR one (ab) row per lane, then the block written in the
+// caller's shell order, or, in Schwarz mode (a.Q set, items (pair, pair)),
+// Q = sqrt(max_{a,b} (ab|ab)) written for the pair.
+// ---------------------------------------------------------------------------
+template <int LA, int LB, int LC, int LD, typename T>
+__global__ __launch_bounds__(64) void k_eri_split(EriLaunch a)
+{
+    using S = EriSplit<LA, LB, LC, LD>;
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    constexpr int NAB = NA * NB, NCD = NC * ND, NF = S::NF, NACC = S::NACC;
+    constexpr int NBUF = NACC > NAB * NCD ? NACC : NAB * NCD;
+    __shared__ double s_buf[NBUF];     // [e][f], then (ab|cd) as [ab][cd]
+    __shared__ double s_abf[NAB * NF]; // (ab|f] as [ab][f]
+    __shared__ double s_tr[16 * 65];
+    static_assert(split_off<LA, LB, LC, LD, S::NPASS>() == NACC, "passes must partition the targets");
+    const int lane = threadIdx.x;
+    double *stage = a.stage + (size_t)blockIdx.x * NACC * 64;
+    const int ngroup = (a.n + 63) / 64;
+    for (int grp = blockIdx.x; grp < ngroup; grp += gridDim.x) {
+        const int t0 = grp * 64;
+        const int nact = min(a.n - t0, 64);
+        const bool active = lane < nact;
+        const EriItem it = a.items[t0 + (active ? lane : 0)];
+        const ShellPairD bra = a.pairs[it.bra];
+        const ShellPairD ket = a.pairs[it.ket];
+        split_passes<LA, LB, LC, LD, 0, T, WK_ONE, true>(bra, ket, a.prims, active, stage, lane, s_tr);
+        __syncthreads();
+        for (int q = 0; q < nact; ++q) {
+            const EriItem iq = a.items[t0 + q];
+            const ShellPairD bq = a.pairs[iq.bra];
+            const ShellPairD kq = a.pairs[iq.ket];
+            for (int t = lane; t < NACC; t += 64) s_buf[split_target<LA, LB, LC, LD>(t)] = stage[(size_t)q * NACC + t];
+            __syncthreads();
+            for (int f = lane; f < NF; f += 64) S::template hrr_bra_col<1, double>(s_buf, f, bq.AB, s_abf);
+            __syncthreads();
+            for (int r = lane; r < NAB; r += 64) {
+                double row[NCD];
+                S::template hrr_ket_row<double>(s_abf + r * NF, kq.AB, row);
+#pragma unroll
+                for (int cd = 0; cd < NCD; ++cd) s_buf[r * NCD + cd] = row[cd];
+            }
+            __syncthreads();
+            if (a.Q) {
+                double mx = 0.0;
+                for (int ab = lane; ab < NAB; ab += 64) mx = fmax(mx, s_buf[ab * NCD + ab]);
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+                if (lane == 0) a.Q[iq.bra] = sqrt(mx);
+            } else {
+                const bool sab = iq.flags & 1, scd = iq.flags & 2, sbk = iq.flags & 4;
+                double *out = a.out + iq.out_off;
+                for (int e = lane; e < NAB * NCD; e += 64) {
+                    const int i = e / (NB * NCD), j = (e / NCD) % NB, k = (e % NCD) / ND, l = e % ND;
+                    int x1, x2, x3, x4;
+                    if (!sbk) {
+                        x1 = sab ? j : i;
+                        x2 = sab ? i : j;
+                        x3 = scd ? l : k;
+                        x4 = scd ? k : l;
+                    } else {
+                        x1 = sab ? l : k;
+                        x2 = sab ? k : l;
+                        x3 = scd ? j : i;
+                        x4 = scd ? i : j;
+                    }
+                    out[((size_t)(x1 * iq.n2 + x2) * iq.n3 + x3) * iq.n4 + x4] = s_buf[e];
+                }
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -991,26 +1091,47 @@ int launch_plain(const JKLaunch &a, hipStream_t s)
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-#define MJK_DEFINE_CLASS_SPLIT(LA, LB, LC, LD, NAME)                                                \
+template <int LA, int LB, int LC, int LD, typename T>
+int launch_eri_split(const EriLaunch &a, hipStream_t s)
+{
+    if (a.n <= 0) return 0;
+    static int grid_cache = 0;  // occupancy bound, computed once
+    if (grid_cache == 0) {
+        grid_cache = occupancy_grid(k_eri_split<LA, LB, LC, LD, T>, 0);
+        if (grid_cache <= 0) return kLaunchHip;
+    }
+    const int64_t grid = persistent_blocks(grid_cache, a.nslot, (a.n + 63) / 64, true);
+    if (grid < 1 || !staging_fits(grid, (int64_t)EriSplit<LA, LB, LC, LD>::NACC * 64, a.stage_bytes))
+        return kLaunchStaging;
+    hipLaunchKernelGGL((k_eri_split<LA, LB, LC, LD, T>), dim3((unsigned)grid), dim3(64), 0, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : kLaunchHip;
+}
+
+// Classes with an f shell have no FP32 form: their "FP32" launchers run the
+// FP64 kernels (the host never routes their quartets to FP32 lists).
+template <int LA, int LB, int LC, int LD>
+using fp32_of = std::conditional_t<(LA == 3 || LB == 3 || LC == 3 || LD == 3), double, float>;
+
+// split classes: J/K launchers and eri_class / Schwarz launchers in separate
+// translation units (they compile in parallel)
+#define MJK_DEFINE_CLASS_SPLIT_JK(LA, LB, LC, LD, NAME)                                             \
     int launch_jk_##NAME(const JKLaunch &a, hipStream_t s)                                         \
     {                                                                                               \
         return launch_split<LA, LB, LC, LD, double>(a, s);                                          \
     }                                                                                               \
     int launch_jk32_##NAME(const JKLaunch &a, hipStream_t s)                                       \
     {                                                                                               \
-        return launch_split<LA, LB, LC, LD, float>(a, s);                                           \
-    }                                                                                               \
+        return launch_split<LA, LB, LC, LD, fp32_of<LA, LB, LC, LD>>(a, s);                         \
+    }
+
+#define MJK_DEFINE_CLASS_SPLIT_ERI(LA, LB, LC, LD, NAME)                                            \
     int launch_eri_##NAME(const EriLaunch &a, hipStream_t s)                                       \
     {                                                                                               \
-        if (a.n <= 0) return 0;                                                                     \
-        hipLaunchKernelGGL((k_eri<LA, LB, LC, LD, double>), dim3((a.n + 63) / 64), dim3(64), 0, s, a); \
-        return hipGetLastError() == hipSuccess ? 0 : -1;                                            \
+        return launch_eri_split<LA, LB, LC, LD, double>(a, s);                                      \
     }                                                                                               \
     int launch_eri32_##NAME(const EriLaunch &a, hipStream_t s)                                     \
     {                                                                                               \
-        if (a.n <= 0) return 0;                                                                     \
-        hipLaunchKernelGGL((k_eri<LA, LB, LC, LD, float>), dim3((a.n + 63) / 64), dim3(64), 0, s, a); \
-        return hipGetLastError() == hipSuccess ? 0 : -1;                                            \
+        return launch_eri_split<LA, LB, LC, LD, fp32_of<LA, LB, LC, LD>>(a, s);                     \
     }
 
 #define MJK_DEFINE_CLASS(LA, LB, LC, LD, NAME)                                                      \

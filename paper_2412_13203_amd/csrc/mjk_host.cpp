@@ -129,6 +129,7 @@ constexpr int kNumKBuckets = 6;
 constexpr int kChunk = 64;          // kets per work item and quartet per lane
 constexpr int kMaxQpl = 16;         // largest quartets-per-lane setting
 constexpr int kEriStage = 65536;    // eri_class items per upload
+constexpr int kEriSlots = 8;        // staging slots for eri_class / Schwarz without the plan's own
 constexpr int kSlotsPerCU = 8;      // resident waves per CU the staging is sized for
 constexpr int kGradMaxAtoms = 1024; // gradient: per-block copy of the gradient in LDS
 
@@ -208,7 +209,7 @@ struct mjk_plan {
     bool dens_screen = false;            // work lists carry a density-weighted screen
     // workspace layout (byte offsets)
     size_t o_xyz, o_atom, o_poff, o_np, o_exps, o_coefs, o_pnat, o_psort, o_prims, o_Q, o_cls, o_work, o_runs,
-        o_segs, o_queue, o_eri, o_rowmax, o_stage, total;
+        o_segs, o_queue, o_eri, o_rowmax, o_stage, o_stage_eri, total;
     size_t max_runs = 0;      // kept-run records: bound over all screening outcomes
     int nslot = 0;            // staging slots for split classes (0 with MJK_FLAG_NO_STAGING)
     int nslot_max = 0;        // slots a launch of this plan can use (occupancy bound)
@@ -254,6 +255,24 @@ struct mjk_batch {
 };
 
 namespace {
+
+// Staging slots that eri_class and the Schwarz factors of split classes use:
+// the plan's own (J/K) slots, or its small eri region.
+struct StageView {
+    double *ptr;
+    size_t bytes;
+    int nslot;
+};
+
+StageView eri_stage(const mjk_plan *p)
+{
+    if (p->nslot > 0) return {(double *)(p->ws + p->o_stage), p->stage_bytes(), p->nslot};
+    const size_t slot = sizeof(double) * 64 * p->stage_nacc;
+    return {(double *)(p->ws + p->o_stage_eri), slot * kEriSlots, slot ? kEriSlots : 0};
+}
+
+// Classes with an f shell run in FP64 whatever fp32_tau is.
+inline bool fp32_allowed(const ClassEntry &ce) { return std::max(std::max(ce.la, ce.lb), std::max(ce.lc, ce.ld)) < 3; }
 
 // chunk prefix and item count of every work list of class `qcls` (-1: all)
 // for the plan's quartets-per-lane table
@@ -741,6 +760,9 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
     p->o_eri = take(sizeof(EriItem) * kEriStage);
     p->o_rowmax = take(sizeof(double) * p->nbf);
     p->o_stage = take(p->stage_bytes());
+    // plans without staging slots of their own (batch members, MJK_FLAG_NO_STAGING)
+    // keep a few for eri_class and the Schwarz factors of split classes
+    p->o_stage_eri = take(p->nslot == 0 ? sizeof(double) * 64 * p->stage_nacc * kEriSlots : 0);
     p->total = off;
 
     p->stats.nbf = p->nbf;
@@ -806,6 +828,7 @@ static int build_lists(mjk_plan *p, const double *shell_w, double tau_w, hipStre
         const Bin &X = p->bins[bp.X], &Y = p->bins[bp.Y];
         const auto &yr = bin_runs[bp.Y];
         const ClassEntry &ce = kClassTable[bp.qcls];
+        const double t32 = fp32_allowed(ce) ? tau32 : 0.0;
         int32_t *c64 = p->work.data() + l64.off, *rb64 = c64 + X.count;
         int32_t *c32 = p->work.data() + l32.off, *rb32 = c32 + X.count;
         std::vector<int64_t> ynp(Y.count + 1, 0);  // prefix of K_C K_D over the ket bin
@@ -829,7 +852,7 @@ static int build_lists(mjk_plan *p, const double *shell_w, double tau_w, hipStre
                 int keep = kept_len(Y, run.first, len, qb, tau);
                 // density-weighted screen: Q_AB Q_CD max(w_A, w_B, w_C, max_D w_D) >= tau_w
                 if (shell_w) keep = kept_len(Y, run.first, keep, qb * std::max(wb, run_w[bp.Y][ri]), tau_w);
-                const int k64 = tau32 > 0.0 ? std::min(keep, kept_len(Y, run.first, keep, qb, tau32)) : keep;
+                const int k64 = t32 > 0.0 ? std::min(keep, kept_len(Y, run.first, keep, qb, t32)) : keep;
                 if (k64 > 0) {
                     runs.push_back({n64, run.first});
                     n64 += k64;
@@ -931,10 +954,37 @@ static int plan_bind(mjk_plan *p, void *workspace, size_t bytes, hipStream_t s)
     HIP_TRY(hipMemcpyAsync(didx, cls_idx.data(), sizeof(int32_t) * cls_idx.size(), hipMemcpyHostToDevice, s));
     for (int q = 0; q < kNumQuartetClasses; ++q) {
         const ClassEntry &ce = kClassTable[q];
-        if (!ce.schwarz) continue;
+        if (ce.la != ce.lc || ce.lb != ce.ld) continue;
         const int c = pair_class(ce.la, ce.lb);
-        SchwarzLaunch sl{pnat, prims, didx + cls_off[c], (int32_t)(cls_off[c + 1] - cls_off[c]), dQ};
-        if (ce.schwarz(sl, s)) return fail(MJK_ERR_HIP, "mjk_plan_bind: Schwarz launch failed");
+        const int n = (int)(cls_off[c + 1] - cls_off[c]);
+        if (n == 0) continue;
+        if (ce.schwarz) {
+            SchwarzLaunch sl{pnat, prims, didx + cls_off[c], n, dQ};
+            if (ce.schwarz(sl, s)) return fail(MJK_ERR_HIP, "mjk_plan_bind: Schwarz launch failed");
+            continue;
+        }
+        // split class: diagonal quartets (AB|AB) through its eri launcher in Schwarz mode
+        const StageView st = eri_stage(p);
+        std::vector<EriItem> items(n);
+        for (int i = 0; i < n; ++i) {
+            EriItem it{};
+            it.bra = it.ket = p->class_pairs[c][i];
+            it.n1 = it.n3 = ncart_h(ce.la);
+            it.n2 = it.n4 = ncart_h(ce.lb);
+            items[i] = it;
+        }
+        auto *stage_items = (EriItem *)(w + p->o_eri);
+        for (int i0 = 0; i0 < n; i0 += kEriStage) {
+            const int m = std::min(kEriStage, n - i0);
+            HIP_TRY(hipMemcpyAsync(stage_items, items.data() + i0, sizeof(EriItem) * m, hipMemcpyHostToDevice, s));
+            EriLaunch el{pnat, prims, stage_items, m, nullptr, st.ptr, st.bytes, st.nslot, dQ};
+            const int rc = ce.eri(el, s);
+            if (rc == kLaunchStaging)
+                return fail(MJK_ERR_STATE, "mjk_plan_bind: Schwarz factors of class (%d%d|%d%d): staging region of "
+                            "%zu bytes too small", ce.la, ce.lb, ce.lc, ce.ld, st.bytes);
+            if (rc) return fail(MJK_ERR_HIP, "mjk_plan_bind: Schwarz launch failed");
+            HIP_TRY(hipStreamSynchronize(s));  // the staged items are rewritten by the next chunk
+        }
     }
     p->Q.resize(p->npair);
     HIP_TRY(hipMemcpyAsync(p->Q.data(), dQ, sizeof(double) * p->npair, hipMemcpyDeviceToHost, s));
@@ -1204,7 +1254,7 @@ int mjk_eri_class(mjk_plan *p, const int32_t *quartets, int64_t nq, double *out,
         it.n4 = ncart_h(p->l[sh[3]]);
         total += (int64_t)it.n1 * it.n2 * it.n3 * it.n4;
         const int qc = quartet_class(p->pairs_nat[bra].cls, p->pairs_nat[ket].cls);
-        const bool f32 = tau32 > 0.0 && p->Q[bra] * p->Q[ket] < tau32;
+        const bool f32 = tau32 > 0.0 && fp32_allowed(kClassTable[qc]) && p->Q[bra] * p->Q[ket] < tau32;
         groups[2 * qc + (f32 ? 1 : 0)].push_back(it);
     }
     if (total != out_len)
@@ -1222,9 +1272,14 @@ int mjk_eri_class(mjk_plan *p, const int32_t *quartets, int64_t nq, double *out,
             const int n = (int)std::min<size_t>(kEriStage, g.size() - i0);
             // stream order keeps this copy behind the previous launch that read the stage
             HIP_TRY(hipMemcpyAsync(stage, g.data() + i0, sizeof(EriItem) * n, hipMemcpyHostToDevice, s));
-            EriLaunch a{(const ShellPairD *)(w + p->o_pnat), (const PrimPairD *)(w + p->o_prims), stage, n, out};
-            if ((gi % 2 ? kClassTable[qc].eri32 : kClassTable[qc].eri)(a, s))
-                return fail(MJK_ERR_HIP, "mjk_eri_class: launch failed");
+            const StageView st = eri_stage(p);
+            EriLaunch a{(const ShellPairD *)(w + p->o_pnat), (const PrimPairD *)(w + p->o_prims), stage, n, out,
+                        st.ptr, st.bytes, st.nslot, nullptr};
+            const int rc = (gi % 2 ? kClassTable[qc].eri32 : kClassTable[qc].eri)(a, s);
+            if (rc == kLaunchStaging)
+                return fail(MJK_ERR_STATE, "mjk_eri_class: staging region of %zu bytes too small for class %d",
+                            st.bytes, qc);
+            if (rc) return fail(MJK_ERR_HIP, "mjk_eri_class: launch failed");
             HIP_TRY(hipStreamSynchronize(s));  // the host vector g is pageable and reused
         }
     }

@@ -97,6 +97,13 @@ struct EriLaunch {
     const EriItem *items;
     int32_t n;
     double *out;
+    // split classes: per-block staging slots of [e0|f0] (persistent blocks)
+    double *stage;
+    size_t stage_bytes;
+    int32_t nslot;
+    // Schwarz mode (split diagonal classes): items are (pair, pair) and
+    // Q[bra] = sqrt(max_{a,b} (ab|ab)) is written instead of `out`
+    double *Q;
 };
 
 struct SchwarzLaunch {

@@ -792,9 +792,9 @@ def _class_job(args):
     (la, lb, lc, ld), (fwd, grad) = args
     gmax = GRAD_MAX_ACC_LOW_L if la + lb + lc + ld <= GRAD_LOW_L_MAX else GRAD_MAX_ACC
     cc = ClassCode(la, lb, lc, ld, max_acc=MAX_ACC if fwd else gmax, passes=grad)
-    # a class the J/K path runs keeps its single-pass code (eri_class and
-    # Schwarz use it); a split class used only by the gradient needs passes
-    full = fwd or not cc.split
+    # single-pass code only where one lane holds the class: split classes run
+    # J/K, eri_class and Schwarz through their passes and the cooperative HRR
+    full = not cc.split
     body = [HEADER]
     if full:
         body.append(cc.emit_vrr())
@@ -841,16 +841,22 @@ def generate(outdir, lmax=2, jobs=None, grad_lmax=2):
     for c in fwd:
         name = cls_name(*c)
         split = infos[c]["split"]
-        lines = ["// Generated by paper_2412_13203_amd/gen/eri_gen.py -- do not edit.",
-                 '#include "../kernels.hpp"', "namespace mjk {", f'#include "cls_{name}.inc"',
-                 (f"MJK_DEFINE_CLASS_SPLIT({c[0]}, {c[1]}, {c[2]}, {c[3]}, {name})" if split else
-                  f"MJK_DEFINE_CLASS({c[0]}, {c[1]}, {c[2]}, {c[3]}, {name})")]
-        if c[:2] == c[2:]:
-            lines.append(f"MJK_DEFINE_SCHWARZ({c[0]}, {c[1]}, {name[:2]})")
-        lines.append("}  // namespace mjk")
-        path = os.path.join(outdir, f"tu_{name}.hip")
-        _write(path, "\n".join(lines) + "\n")
-        tus.append(path)
+        head = ["// Generated by paper_2412_13203_amd/gen/eri_gen.py -- do not edit.",
+                '#include "../kernels.hpp"', "namespace mjk {", f'#include "cls_{name}.inc"']
+        units = []
+        if split:
+            # J/K and eri_class/Schwarz kernels of a split class in two units
+            units.append(("", [f"MJK_DEFINE_CLASS_SPLIT_JK({c[0]}, {c[1]}, {c[2]}, {c[3]}, {name})"]))
+            units.append(("eri_", [f"MJK_DEFINE_CLASS_SPLIT_ERI({c[0]}, {c[1]}, {c[2]}, {c[3]}, {name})"]))
+        else:
+            body = [f"MJK_DEFINE_CLASS({c[0]}, {c[1]}, {c[2]}, {c[3]}, {name})"]
+            if c[:2] == c[2:]:
+                body.append(f"MJK_DEFINE_SCHWARZ({c[0]}, {c[1]}, {name[:2]})")
+            units.append(("", body))
+        for prefix, body in units:
+            path = os.path.join(outdir, f"tu_{prefix}{name}.hip")
+            _write(path, "\n".join(head + body + ["}  // namespace mjk"]) + "\n")
+            tus.append(path)
         if not has_grad(c):
             continue
         lines = ["// Generated by paper_2412_13203_amd/gen/eri_gen.py -- do not edit.",
@@ -874,7 +880,7 @@ def generate(outdir, lmax=2, jobs=None, grad_lmax=2):
         if has_grad(c):
             d.append(f"int launch_grad_{name}(const JKLaunch &, hipStream_t);")
             d.append(f"size_t grad_stage_nacc_{name}();")
-        if c[:2] == c[2:]:
+        if c[:2] == c[2:] and not infos[c]["split"]:
             d.append(f"int launch_schwarz_{name[:2]}(const SchwarzLaunch &, hipStream_t);")
     d.append(f"constexpr int kLmax = {lmax};")
     d.append(f"constexpr int kGradLmax = {grad_lmax};")
@@ -884,7 +890,8 @@ def generate(outdir, lmax=2, jobs=None, grad_lmax=2):
     for c in fwd:
         name = cls_name(*c)
         cc = infos[c]
-        sch = f"launch_schwarz_{name[:2]}" if c[:2] == c[2:] else "nullptr"
+        # split diagonal classes compute Schwarz factors through their eri launcher
+        sch = f"launch_schwarz_{name[:2]}" if c[:2] == c[2:] and not cc["split"] else "nullptr"
         # algorithmic work: the single-pass recurrence and the cheaper HRR order,
         # whatever the kernel executes (passes recompute shared intermediates)
         subs = grad_subclasses(*c) if has_grad(c) else []
