@@ -207,6 +207,10 @@ struct mjk_plan {
     std::vector<ShellPairD> psort;
     std::vector<std::vector<std::pair<int, int>>> bin_runs;
     bool dens_screen = false;            // work lists carry a density-weighted screen
+    // staging lent by a batch while it binds its molecules (Schwarz factors of split classes)
+    double *lent_stage = nullptr;
+    size_t lent_stage_bytes = 0;
+    int lent_nslot = 0;
     // workspace layout (byte offsets)
     size_t o_xyz, o_atom, o_poff, o_np, o_exps, o_coefs, o_pnat, o_psort, o_prims, o_Q, o_cls, o_work, o_runs,
         o_segs, o_queue, o_eri, o_rowmax, o_stage, o_stage_eri, total;
@@ -267,6 +271,7 @@ struct StageView {
 StageView eri_stage(const mjk_plan *p)
 {
     if (p->nslot > 0) return {(double *)(p->ws + p->o_stage), p->stage_bytes(), p->nslot};
+    if (p->lent_nslot > 0) return {p->lent_stage, p->lent_stage_bytes, p->lent_nslot};
     const size_t slot = sizeof(double) * 64 * p->stage_nacc;
     return {(double *)(p->ws + p->o_stage_eri), slot * kEriSlots, slot ? kEriSlots : 0};
 }
@@ -760,9 +765,10 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
     p->o_eri = take(sizeof(EriItem) * kEriStage);
     p->o_rowmax = take(sizeof(double) * p->nbf);
     p->o_stage = take(p->stage_bytes());
-    // plans without staging slots of their own (batch members, MJK_FLAG_NO_STAGING)
-    // keep a few for eri_class and the Schwarz factors of split classes
-    p->o_stage_eri = take(p->nslot == 0 ? sizeof(double) * 64 * p->stage_nacc * kEriSlots : 0);
+    // plans created with MJK_FLAG_NO_STAGING keep a few staging slots for
+    // eri_class and the Schwarz factors of split classes (batch members
+    // borrow the batch's staging while it binds them)
+    p->o_stage_eri = take(p->nslot == 0 && !in_batch ? sizeof(double) * 64 * p->stage_nacc * kEriSlots : 0);
     p->total = off;
 
     p->stats.nbf = p->nbf;
@@ -1448,7 +1454,16 @@ int mjk_batch_bind(mjk_batch *b, void *workspace, size_t bytes, void *stream)
     for (size_t m = 0; m < b->plans.size(); ++m) {
         mjk_plan *p = b->plans[m];
         for (int q = 0; q < kNumQuartetClasses; ++q) p->qpl[q] = b->qpl[q];
-        if (int rc = plan_bind(p, b->ws + b->ws_off[m], p->total, s)) return rc;
+        // the batch's staging serves the molecule's Schwarz factors (binds are
+        // synchronous, so the molecules take it in turn)
+        p->lent_stage = (double *)(b->ws + b->o_stage);
+        p->lent_stage_bytes = b->stage_bytes();
+        p->lent_nslot = b->nslot;
+        const int rc = plan_bind(p, b->ws + b->ws_off[m], p->total, s);
+        p->lent_stage = nullptr;
+        p->lent_stage_bytes = 0;
+        p->lent_nslot = 0;
+        if (rc) return rc;
     }
     if (int rc = batch_regroup(b, s)) return rc;
     b->bound = true;
