@@ -60,6 +60,9 @@ extern "C" {
 #define MJK_FLAG_NO_STAGING 0x4u  /* no staging slots or work counters in the workspace: the plan
                                    * builds J and K with mjk_build_jk_static only (not with
                                    * MJK_FLAG_GRAD, not in batches)                              */
+#define MJK_FLAG_PERSISTENT 0x8u  /* J/K builds: the per-lane classes run persistent waves that
+                                   * take work items from the launch's counter (the split classes
+                                   * always do); without it, one block per work item             */
 
 typedef struct mjk_ctx mjk_ctx;
 typedef struct mjk_plan mjk_plan;

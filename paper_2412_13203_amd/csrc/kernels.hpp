@@ -343,7 +343,7 @@ __device__ __forceinline__ void stamp(const JKLaunch &a, int mol, int lane, bool
 
 // ---------------------------------------------------------------------------
 // Fused J/K: one wave = one bra pair (uniform) x up to 64 ket pairs per
-// round (one per lane), `chunk` kets per item.  Digestion of (ab|cd) with the 8-fold symmetry of a
+// round (one per lane), `chunk` kets per item; persistent waves pop items.  Digestion of (ab|cd) with the 8-fold symmetry of a
 // unique quartet, weight w = 1/(s_AB s_CD s_ABCD):
 //   Jt_ab += 2w D_cd   Jt_cd += 2w D_ab
 //   Kt_ac += w D_bd    Kt_ad += w D_bc    Kt_bc += w D_ad    Kt_bd += w D_ac
@@ -353,11 +353,10 @@ __device__ __forceinline__ void stamp(const JKLaunch &a, int mol, int lane, bool
 // of one run (same C) and added once per run.
 // ---------------------------------------------------------------------------
 template <int LA, int LB, int LC, int LD, typename T>
-__device__ __forceinline__ void jk_lane_body(const JKLaunch &a)
+__device__ __forceinline__ void jk_lane_item(const JKLaunch &a, int item)
 {
     using C = EriClass<LA, LB, LC, LD>;
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
-    const int item = blockIdx.x;
     const int lane = threadIdx.x;
     const JKSeg sg = ldg(a.segs + find_seg(a, item));
     int b, kbeg, kend;
@@ -493,6 +492,24 @@ __device__ __forceinline__ void jk_lane_body(const JKLaunch &a)
         if (lane == 0) atomicAdd(Jm + (size_t)(bra.ao_a + ab / NB) * N + bra.ao_b + ab % NB, t);
     }
     stamp(a, sg.mol, lane, true);
+}
+
+// One block per item, or (lane_persistent) persistent waves that take items
+// from the launch's counter until none are left (the launch's grid is then
+// the occupancy bound, cut to the items).
+template <int LA, int LB, int LC, int LD, typename T>
+__device__ __forceinline__ void jk_lane_body(const JKLaunch &a)
+{
+    if (!a.lane_persistent) {
+        jk_lane_item<LA, LB, LC, LD, T>(a, blockIdx.x);
+        return;
+    }
+    const int lane = threadIdx.x;
+    for (;;) {
+        const int item = next_item(a, lane);
+        if (item >= a.nitems) break;
+        jk_lane_item<LA, LB, LC, LD, T>(a, item);
+    }
 }
 
 // Resident waves per SIMD asked of the compiler for a few per-lane classes
@@ -949,11 +966,60 @@ __device__ __forceinline__ void jk_split_body(const JKLaunch &a)
     }
 }
 
+// Passes of one quartet with its primitive quartets spread over the wave
+// (the contraction of Eq. 2 summed across the lanes): pass P's targets go to
+// positions split_off<P> + j of the quartet's slot `sq` (pass order).
+template <int LA, int LB, int LC, int LD, int P, typename T>
+__device__ __forceinline__ void split_passes_prim(const ShellPairD &bra, const ShellPairD &ket,
+                                                  const PrimPairD *__restrict__ prims, double *__restrict__ sq,
+                                                  int lane)
+{
+    using S = EriSplit<LA, LB, LC, LD>;
+    if constexpr (P < S::NPASS) {
+        constexpr int L = LA + LB + LC + LD;
+        constexpr int NP = S::template npass_acc<P>(), O = split_off<LA, LB, LC, LD, P>();
+        T acc[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) acc[i] = T(0);
+        const int nb = bra.nprim, npq = nb * ket.nprim;
+        for (int ip = lane; ip < npq; ip += 64) {
+            const PrimPairD kp = load_prim(prims + ket.prim_off + ip / nb);
+            const PrimPairD bp = load_prim(prims + bra.prim_off + ip % nb);
+            VrrGeom<double> g;
+            double Tb;
+            const double pref = prim_geom(bp, kp, g, Tb);
+            double F[L + 1];
+            boys_fm<L>(Tb, F);
+#pragma unroll
+            for (int m = 0; m <= L; ++m) F[m] *= pref;
+            if constexpr (sizeof(T) == sizeof(double)) {
+                S::template vrr<P, double>(F, g, acc);
+            } else {
+                T Ft[L + 1];
+#pragma unroll
+                for (int m = 0; m <= L; ++m) Ft[m] = (T)F[m];
+                VrrGeom<T> h;
+                to_type(g, h);
+                S::template vrr<P, T>(Ft, h, acc);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            T v = acc[j];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) sq[O + j] = (double)v;
+        }
+        split_passes_prim<LA, LB, LC, LD, P + 1, T>(bra, ket, prims, sq, lane);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Explicit ERI blocks (and Schwarz factors) of classes split into recurrence
 // passes: persistent blocks take 64 requested quartets at a time; phase 1 as
 // in the split J/K kernel (one quartet per lane, passes into the block's
-// staging slot), phase 2 one quartet at a time: bra HRR one ket column per
+// staging slot), or, with `deconstruct`, one quartet at a time with its
+// primitive quartets spread over the lanes; phase 2 one quartet at a time: bra HRR one ket column per
 // lane, ket HRR one (ab) row per lane, then the block written in the
 // caller's shell order, or, in Schwarz mode (a.Q set, items (pair, pair)),
 // Q = sqrt(max_{a,b} (ab|ab)) written for the pair.
@@ -971,15 +1037,21 @@ __global__ __launch_bounds__(64) void k_eri_split(EriLaunch a)
     static_assert(split_off<LA, LB, LC, LD, S::NPASS>() == NACC, "passes must partition the targets");
     const int lane = threadIdx.x;
     double *stage = a.stage + (size_t)blockIdx.x * NACC * 64;
-    const int ngroup = (a.n + 63) / 64;
+    const int gsize = a.deconstruct ? 1 : 64;  // quartets per group
+    const int ngroup = (a.n + gsize - 1) / gsize;
     for (int grp = blockIdx.x; grp < ngroup; grp += gridDim.x) {
-        const int t0 = grp * 64;
-        const int nact = min(a.n - t0, 64);
-        const bool active = lane < nact;
-        const EriItem it = a.items[t0 + (active ? lane : 0)];
-        const ShellPairD bra = a.pairs[it.bra];
-        const ShellPairD ket = a.pairs[it.ket];
-        split_passes<LA, LB, LC, LD, 0, T, WK_ONE, true>(bra, ket, a.prims, active, stage, lane, s_tr);
+        const int t0 = grp * gsize;
+        const int nact = min(a.n - t0, gsize);
+        if (a.deconstruct) {
+            const EriItem it = a.items[t0];
+            split_passes_prim<LA, LB, LC, LD, 0, T>(a.pairs[it.bra], a.pairs[it.ket], a.prims, stage, lane);
+        } else {
+            const bool active = lane < nact;
+            const EriItem it = a.items[t0 + (active ? lane : 0)];
+            const ShellPairD bra = a.pairs[it.bra];
+            const ShellPairD ket = a.pairs[it.ket];
+            split_passes<LA, LB, LC, LD, 0, T, WK_ONE, true>(bra, ket, a.prims, active, stage, lane, s_tr);
+        }
         __syncthreads();
         for (int q = 0; q < nact; ++q) {
             const EriItem iq = a.items[t0 + q];
@@ -1084,11 +1156,20 @@ int launch_plain(const JKLaunch &a, hipStream_t s)
 {
     if (a.nitems <= 0) return 0;
     constexpr int W = jk_waves<LA, LB, LC, LD>();
+    static int grid_cache = 0;  // occupancy bound, computed once
+    if (grid_cache == 0) {
+        if constexpr (W > 0)
+            grid_cache = occupancy_grid(k_jk_occ<LA, LB, LC, LD, T, W>, 0);
+        else
+            grid_cache = occupancy_grid(k_jk<LA, LB, LC, LD, T>, 0);
+        if (grid_cache <= 0) return kLaunchHip;
+    }
+    const int64_t grid = a.lane_persistent ? persistent_blocks(grid_cache, 0, a.nitems, false) : a.nitems;
     if constexpr (W > 0)
-        hipLaunchKernelGGL((k_jk_occ<LA, LB, LC, LD, T, W>), dim3(a.nitems), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((k_jk_occ<LA, LB, LC, LD, T, W>), dim3((unsigned)grid), dim3(64), 0, s, a);
     else
-        hipLaunchKernelGGL((k_jk<LA, LB, LC, LD, T>), dim3(a.nitems), dim3(64), 0, s, a);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+        hipLaunchKernelGGL((k_jk<LA, LB, LC, LD, T>), dim3((unsigned)grid), dim3(64), 0, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : kLaunchHip;
 }
 
 template <int LA, int LB, int LC, int LD, typename T>
@@ -1100,7 +1181,8 @@ int launch_eri_split(const EriLaunch &a, hipStream_t s)
         grid_cache = occupancy_grid(k_eri_split<LA, LB, LC, LD, T>, 0);
         if (grid_cache <= 0) return kLaunchHip;
     }
-    const int64_t grid = persistent_blocks(grid_cache, a.nslot, (a.n + 63) / 64, true);
+    const int64_t groups = a.deconstruct ? a.n : (a.n + 63) / 64;
+    const int64_t grid = persistent_blocks(grid_cache, a.nslot, groups, true);
     if (grid < 1 || !staging_fits(grid, (int64_t)EriSplit<LA, LB, LC, LD>::NACC * 64, a.stage_bytes))
         return kLaunchStaging;
     hipLaunchKernelGGL((k_eri_split<LA, LB, LC, LD, T>), dim3((unsigned)grid), dim3(64), 0, s, a);

@@ -130,6 +130,7 @@ constexpr int kChunk = 64;          // kets per work item and quartet per lane
 constexpr int kMaxQpl = 16;         // largest quartets-per-lane setting
 constexpr int kEriStage = 65536;    // eri_class items per upload
 constexpr int kEriSlots = 8;        // staging slots for eri_class / Schwarz without the plan's own
+constexpr int kEriDeconstructMax = 4096;  // eri_class: split-class groups up to this size run one quartet per block
 constexpr int kSlotsPerCU = 8;      // resident waves per CU the staging is sized for
 constexpr int kGradMaxAtoms = 1024; // gradient: per-block copy of the gradient in LDS
 
@@ -409,7 +410,8 @@ int ensure_events(std::vector<hipEvent_t> &ev, size_t n)
 // cleared the outputs; the work counters are cleared here.
 int run_groups(const std::vector<Group> &gs, const JKSeg *dsegs, uint32_t *dqueue, double *stage, size_t stage_bytes,
                int nslot, const double *D, double *J, double *K, double *grad, int natom_max,
-               unsigned long long *stamps, hipStream_t s, std::vector<hipEvent_t> *ev, const char *who)
+               unsigned long long *stamps, hipStream_t s, std::vector<hipEvent_t> *ev, const char *who,
+               bool lane_persistent = false)
 {
     if (gs.empty()) return MJK_OK;
     if (launch_fill_u32(dqueue, (int64_t)gs.size(), 0u, s)) return fail(MJK_ERR_HIP, "%s: fill launch failed", who);
@@ -429,6 +431,7 @@ int run_groups(const std::vector<Group> &gs, const JKSeg *dsegs, uint32_t *dqueu
         a.natom_max = natom_max;
         a.queue = dqueue + i;
         a.stamps = stamps;
+        a.lane_persistent = lane_persistent ? 1 : 0;
         const ClassEntry &ce = kClassTable[g.qcls];
         if (ev) HIP_TRY(hipEventRecord((*ev)[2 * i], s));
         if (grad && !ce.grad) return fail(MJK_ERR_UNSUPPORTED, "%s: no gradient kernel for this class", who);
@@ -615,7 +618,7 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
         return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: schwarz_tau = %g", o.schwarz_tau);
     if (!(std::isfinite(o.fp32_tau) && o.fp32_tau >= 0.0))
         return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: fp32_tau = %g", o.fp32_tau);
-    if (o.flags & ~(MJK_FLAG_CHECK | MJK_FLAG_GRAD | MJK_FLAG_NO_STAGING))
+    if (o.flags & ~(MJK_FLAG_CHECK | MJK_FLAG_GRAD | MJK_FLAG_NO_STAGING | MJK_FLAG_PERSISTENT))
         return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: unknown flags 0x%x", o.flags);
     if ((o.flags & MJK_FLAG_NO_STAGING) && (in_batch || (o.flags & MJK_FLAG_GRAD)))
         return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: MJK_FLAG_NO_STAGING is for single J/K plans only");
@@ -983,7 +986,8 @@ static int plan_bind(mjk_plan *p, void *workspace, size_t bytes, hipStream_t s)
         for (int i0 = 0; i0 < n; i0 += kEriStage) {
             const int m = std::min(kEriStage, n - i0);
             HIP_TRY(hipMemcpyAsync(stage_items, items.data() + i0, sizeof(EriItem) * m, hipMemcpyHostToDevice, s));
-            EriLaunch el{pnat, prims, stage_items, m, nullptr, st.ptr, st.bytes, st.nslot, dQ};
+            // few quartets, each with up to 6^4 primitive quartets: spread those over the lanes
+            EriLaunch el{pnat, prims, stage_items, m, nullptr, st.ptr, st.bytes, st.nslot, dQ, 1};
             const int rc = ce.eri(el, s);
             if (rc == kLaunchStaging)
                 return fail(MJK_ERR_STATE, "mjk_plan_bind: Schwarz factors of class (%d%d|%d%d): staging region of "
@@ -1117,7 +1121,8 @@ static int build_jk_run(mjk_plan *p, const double *D, double *J, double *K, hipS
     p->timed_last = timed;
     p->timed_grad = false;
     if (int rc = run_groups(p->groups, (const JKSeg *)(p->ws + p->o_segs), queue, stage, stage_bytes, nslot, D, J, K,
-                            nullptr, 0, nullptr, s, timed ? &p->ev : nullptr, who))
+                            nullptr, 0, nullptr, s, timed ? &p->ev : nullptr, who,
+                            (p->opts.flags & MJK_FLAG_PERSISTENT) != 0))
         return rc;
     if (launch_symmetrize(J, p->nbf, s) || launch_symmetrize(K, p->nbf, s))
         return fail(MJK_ERR_HIP, "%s: symmetrize launch failed", who);
@@ -1279,8 +1284,9 @@ int mjk_eri_class(mjk_plan *p, const int32_t *quartets, int64_t nq, double *out,
             // stream order keeps this copy behind the previous launch that read the stage
             HIP_TRY(hipMemcpyAsync(stage, g.data() + i0, sizeof(EriItem) * n, hipMemcpyHostToDevice, s));
             const StageView st = eri_stage(p);
+            // split classes: few requested quartets run one per block, primitive quartets over the lanes
             EriLaunch a{(const ShellPairD *)(w + p->o_pnat), (const PrimPairD *)(w + p->o_prims), stage, n, out,
-                        st.ptr, st.bytes, st.nslot, nullptr};
+                        st.ptr, st.bytes, st.nslot, nullptr, n <= kEriDeconstructMax ? 1 : 0};
             const int rc = (gi % 2 ? kClassTable[qc].eri32 : kClassTable[qc].eri)(a, s);
             if (rc == kLaunchStaging)
                 return fail(MJK_ERR_STATE, "mjk_eri_class: staging region of %zu bytes too small for class %d",
@@ -1522,7 +1528,8 @@ static int batch_run(mjk_batch *b, const double *D, double *J, double *K, hipStr
     b->stamped_last = b->stamps;
     return run_groups(b->groups, (const JKSeg *)(b->ws + b->o_segs), (uint32_t *)(b->ws + b->o_queue),
                       (double *)(b->ws + b->o_stage), b->stage_bytes(), b->nslot, D, J, K, nullptr, 0, st, s,
-                      timed ? &b->ev : nullptr, "mjk_batch_build_jk");
+                      timed ? &b->ev : nullptr, "mjk_batch_build_jk",
+                      (b->plans[0]->opts.flags & MJK_FLAG_PERSISTENT) != 0);
 }
 
 int mjk_batch_build_jk(mjk_batch *b, const double *D, double *J, double *K, void *stream)
@@ -1639,7 +1646,8 @@ int mjk_batch_autotune(mjk_batch *b, const double *D, double *J, double *K, int3
             HIP_TRY(hipEventRecord(e0, s));
             if (int rc = run_groups(sel, (const JKSeg *)(b->ws + b->o_segs), (uint32_t *)(b->ws + b->o_queue),
                                     (double *)(b->ws + b->o_stage), b->stage_bytes(), b->nslot, D, J, K, nullptr, 0,
-                                    nullptr, s, nullptr, "mjk_batch_autotune"))
+                                    nullptr, s, nullptr, "mjk_batch_autotune",
+                                    (b->plans[0]->opts.flags & MJK_FLAG_PERSISTENT) != 0))
                 return rc;
             HIP_TRY(hipEventRecord(e1, s));
             HIP_TRY(hipEventSynchronize(e1));

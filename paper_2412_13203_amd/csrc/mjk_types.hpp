@@ -89,6 +89,7 @@ struct JKLaunch {
     int32_t natom_max;           // gradient: LDS copy of one molecule's gradient
     uint32_t *queue;             // persistent kernels: work counter, zero at launch
     unsigned long long *stamps;  // optional: per molecule [first start, last end]
+    int32_t lane_persistent;     // per-lane classes: persistent waves pop items (else one block per item)
 };
 
 struct EriLaunch {
@@ -104,6 +105,9 @@ struct EriLaunch {
     // Schwarz mode (split diagonal classes): items are (pair, pair) and
     // Q[bra] = sqrt(max_{a,b} (ab|ab)) is written instead of `out`
     double *Q;
+    // split classes: one quartet per block, its primitive quartets spread
+    // over the lanes (for few quartets with many primitives each)
+    int32_t deconstruct;
 };
 
 struct SchwarzLaunch {

@@ -27,6 +27,7 @@ ERRORS = {-1: "MJK_ERR_INVALID_ARG", -2: "MJK_ERR_UNSUPPORTED", -3: "MJK_ERR_NO_
 FLAG_CHECK = 0x1
 FLAG_GRAD = 0x2
 FLAG_NO_STAGING = 0x4
+FLAG_PERSISTENT = 0x8
 
 
 class MjkError(RuntimeError):
@@ -404,14 +405,14 @@ class Batch:
     """Many molecules in one launch per class (mjk_batch_*).  D, J, K of
     molecule m are views into one packed device buffer (offsets())."""
 
-    def __init__(self, bases, tau: float = 0.0, device: int = 0, fp32_tau: float = 0.0):
+    def __init__(self, bases, tau: float = 0.0, device: int = 0, fp32_tau: float = 0.0, flags: int = 0):
         import torch
         self.torch = torch
         self.device = device
         self._hbs = [_HostBasis(b) for b in bases]
         n = len(self._hbs)
         arr = (Basis * n)(*[h.s for h in self._hbs])
-        opts = JKOpts(float(tau), float(fp32_tau), 0)
+        opts = JKOpts(float(tau), float(fp32_tau), int(flags))
         p = ctypes.c_void_p()
         nbytes = ctypes.c_size_t(0)
         _check(lib().mjk_batch_create(context(device), n, arr, ctypes.byref(opts), ctypes.byref(p),
