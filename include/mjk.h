@@ -219,11 +219,17 @@ int mjk_grad_e2(mjk_plan *plan, const double *D, double *grad, void *stream);
 int mjk_e2_backward(mjk_plan *plan, const double *D, const double *J, const double *K, const double *gout,
                     double *gD, double *gR, void *stream);
 
-/* Per-class work per lane (Section 7, Algorithm 2's workload): qpl[q]
- * quartets per lane for class q (1, 2, 4, 8 or 16; n = mjk_num_classes()),
- * i.e. a wave takes one bra pair and 64 * qpl[q] of its kets.  Default 1.
- * Rebuilds the plan's work lists (host, then a synchronous upload; waits for
- * the device to be idle first).  Results change only in summation order. */
+/* Bins of shell pairs by primitive-pair count K_A K_B ("K-buckets": 1, 2-4,
+ * 5-9, 10-16, 17-25, 26-36), inside each angular-momentum class. */
+int mjk_num_kbuckets(void);
+
+/* Work per lane (Section 7, Algorithm 2's workload): quartets per lane
+ * (1, 2, 4, 8 or 16), i.e. a wave takes one bra pair and 64 * qpl of its
+ * kets.  Either one value per class (n = mjk_num_classes(), qpl[q]) or one
+ * per class and bra K-bucket (n = mjk_num_classes() * mjk_num_kbuckets(),
+ * qpl[q * mjk_num_kbuckets() + k]).  Default 1.  Rebuilds the plan's work
+ * lists (host, then a synchronous upload; waits for the device to be idle
+ * first).  Results change only in summation order. */
 int mjk_plan_set_tiles(mjk_plan *plan, const int32_t *qpl, int32_t n);
 
 /* Explicit contracted ERI blocks (Eq. 2) for nq shell quartets.
@@ -312,14 +318,16 @@ void mjk_plan_destroy(mjk_plan *plan);
  * mjk_batch_bind: builds every molecule's tables in the workspace
  *   (synchronizes `stream` once per molecule).
  * mjk_batch_build_jk: J and K of every molecule, overwritten; asynchronous.
- * mjk_batch_set_tiles: per-class quartets per lane, as mjk_plan_set_tiles.
- * mjk_batch_autotune: Algorithm 2 on this batch: all classes start at one
- *   quartet per lane; each sweep times a class alone (shortest of `reps`
- *   launches), doubles its workload (Combine), times it again and keeps the
- *   change if faster, else halves it back (Revert) and leaves the class;
- *   sweeps repeat while any class improved.  The chosen table is written to
- *   qpl_out (n = mjk_num_classes()) and left active.  Synchronous; J and K
- *   hold no meaningful values afterwards.
+ * mjk_batch_set_tiles: quartets per lane, as mjk_plan_set_tiles.
+ * mjk_batch_autotune: Algorithm 2 on this batch.  qpl (in/out, n values)
+ *   is a table per class (n = mjk_num_classes()) or per class and bra
+ *   K-bucket (n = classes x mjk_num_kbuckets()); entries 0 are tuned (they
+ *   start at one quartet per lane), the others stay as given.  Each sweep
+ *   times an entry's class alone (shortest of `reps` launches), doubles the
+ *   entry's workload (Combine), times it again and keeps the change if
+ *   faster, else halves it back (Revert) and retires the entry; sweeps repeat
+ *   while any entry improved.  The result is written back to qpl and left
+ *   active.  Synchronous; J and K hold no meaningful values afterwards.
  * mjk_batch_set_stamps: record per-molecule wall-clock stamps (first work
  *   item started, last work item finished) during builds;
  *   mjk_batch_mol_times converts those of the last build to milliseconds
@@ -335,7 +343,7 @@ int mjk_batch_bind(mjk_batch *batch, void *workspace, size_t bytes, void *stream
 int mjk_batch_offsets(const mjk_batch *batch, int64_t *mat_off);
 int mjk_batch_build_jk(mjk_batch *batch, const double *D, double *J, double *K, void *stream);
 int mjk_batch_set_tiles(mjk_batch *batch, const int32_t *qpl, int32_t n);
-int mjk_batch_autotune(mjk_batch *batch, const double *D, double *J, double *K, int32_t reps, int32_t *qpl_out,
+int mjk_batch_autotune(mjk_batch *batch, const double *D, double *J, double *K, int32_t reps, int32_t *qpl,
                        int32_t n, void *stream);
 int mjk_batch_set_stamps(mjk_batch *batch, int enable);
 int mjk_batch_mol_times(mjk_batch *batch, double *ms);

@@ -202,7 +202,7 @@ struct mjk_plan {
     std::vector<int32_t> work;           // host copy of the work-list region
     std::vector<std::vector<int32_t>> class_pairs;  // natural indices per pair class
     std::vector<int32_t> class_off;      // pair class c: device list entries [class_off[c], class_off[c+1])
-    int qpl[kNumQuartetClasses];         // quartets per lane, per class
+    int qpl[kNumQuartetClasses * kNumKBuckets];  // quartets per lane, per (class, bra K-bucket)
     std::vector<Group> groups;
     // class-sorted pair table (host copy) and the runs of every bin: bin-relative start, length
     std::vector<ShellPairD> psort;
@@ -244,7 +244,7 @@ struct mjk_batch {
     size_t nseg = 0;
     int nslot = 0;
     size_t stage_nacc = 0;
-    int qpl[kNumQuartetClasses];
+    int qpl[kNumQuartetClasses * kNumKBuckets];
     std::vector<Group> groups;
     char *ws = nullptr;
     bool bound = false;
@@ -287,7 +287,7 @@ void rechunk(mjk_plan *p, int qcls)
     for (auto &wl : p->lists) {
         const int qc = p->bps[wl.bp].qcls;
         if (qcls >= 0 && qc != qcls) continue;
-        wl.chunk = kChunk * p->qpl[qc];
+        wl.chunk = kChunk * p->qpl[qc * kNumKBuckets + p->bins[p->bps[wl.bp].X].kb];
         const int32_t *cnt = p->work.data() + wl.off;
         int32_t *pre = p->work.data() + wl.off + 2 * (size_t)wl.nbra + 1;
         pre[0] = 0;
@@ -476,16 +476,23 @@ int fill_timings(const std::vector<Group> &gs, std::vector<hipEvent_t> &ev, bool
     return MJK_OK;
 }
 
-int check_qpl(const int32_t *qpl, int32_t n, const char *who)
+constexpr int kTileUnits = kNumQuartetClasses * kNumKBuckets;
+
+// Validates a tile table of n = classes (one value per class) or n = classes
+// x K-buckets (one per class and bra K-bucket) entries and expands it into
+// the per-unit table `units`.
+int check_qpl(const int32_t *qpl, int32_t n, const char *who, int *units)
 {
-    if (!qpl || n != kNumQuartetClasses)
-        return fail(MJK_ERR_INVALID_ARG, "%s: need %d per-class values", who, kNumQuartetClasses);
+    if (!qpl || (n != kNumQuartetClasses && n != kTileUnits))
+        return fail(MJK_ERR_INVALID_ARG, "%s: need %d per-class or %d per-class-and-bucket values", who,
+                    kNumQuartetClasses, kTileUnits);
     for (int q = 0; q < n; ++q) {
         const int v = qpl[q];
         if (v < 1 || v > kMaxQpl || (v & (v - 1)))
-            return fail(MJK_ERR_INVALID_ARG, "%s: class %d: %d quartets per lane (1, 2, 4, ... %d)", who, q, v,
+            return fail(MJK_ERR_INVALID_ARG, "%s: entry %d: %d quartets per lane (1, 2, 4, ... %d)", who, q, v,
                         kMaxQpl);
     }
+    for (int u = 0; u < kTileUnits; ++u) units[u] = n == kTileUnits ? qpl[u] : qpl[u / kNumKBuckets];
     return MJK_OK;
 }
 
@@ -632,7 +639,7 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
     p->ctx = ctx;
     p->opts = o;
     p->in_batch = in_batch;
-    for (int q = 0; q < kNumQuartetClasses; ++q) p->qpl[q] = 1;
+    for (int q = 0; q < kNumQuartetClasses * kNumKBuckets; ++q) p->qpl[q] = 1;
     p->natom = b->natom;
     p->nshell = b->nshell;
     p->nprim = b->nprim;
@@ -1090,10 +1097,11 @@ int mjk_plan_set_tiles(mjk_plan *p, const int32_t *qpl, int32_t n)
     if (!p) return fail(MJK_ERR_INVALID_ARG, "mjk_plan_set_tiles: plan is NULL");
     CtxScope cs_(p->ctx);
     if (!p->bound) return fail(MJK_ERR_STATE, "mjk_plan_set_tiles: plan is not bound");
-    if (int rc = check_qpl(qpl, n, "mjk_plan_set_tiles")) return rc;
+    int units[kTileUnits];
+    if (int rc = check_qpl(qpl, n, "mjk_plan_set_tiles", units)) return rc;
     HIP_TRY(hipSetDevice(p->ctx->device));
     HIP_TRY(hipDeviceSynchronize());  // no launch of this plan may still read the lists
-    for (int q = 0; q < n; ++q) p->qpl[q] = qpl[q];
+    for (int u = 0; u < kTileUnits; ++u) p->qpl[u] = units[u];
     rechunk(p, -1);
     if (int rc = upload_work(p, nullptr)) return rc;
     p->groups = make_groups({p});
@@ -1400,7 +1408,7 @@ int mjk_batch_create(mjk_ctx *ctx, int32_t nmol, const mjk_basis *mols, const mj
         return fail(MJK_ERR_INVALID_ARG, "mjk_batch_create: batches build J and K only (no MJK_FLAG_GRAD)");
     auto *bt = new mjk_batch;
     bt->ctx = ctx;
-    for (int q = 0; q < kNumQuartetClasses; ++q) bt->qpl[q] = 1;
+    for (int q = 0; q < kNumQuartetClasses * kNumKBuckets; ++q) bt->qpl[q] = 1;
     size_t off = 0;
     int64_t moff = 0, max_items = 0;
     bt->mat_off.push_back(0);
@@ -1459,7 +1467,7 @@ int mjk_batch_bind(mjk_batch *b, void *workspace, size_t bytes, void *stream)
     hipStream_t s = (hipStream_t)stream;
     for (size_t m = 0; m < b->plans.size(); ++m) {
         mjk_plan *p = b->plans[m];
-        for (int q = 0; q < kNumQuartetClasses; ++q) p->qpl[q] = b->qpl[q];
+        for (int q = 0; q < kNumQuartetClasses * kNumKBuckets; ++q) p->qpl[q] = b->qpl[q];
         // the batch's staging serves the molecule's Schwarz factors (binds are
         // synchronous, so the molecules take it in turn)
         p->lent_stage = (double *)(b->ws + b->o_stage);
@@ -1488,12 +1496,13 @@ int mjk_batch_set_tiles(mjk_batch *b, const int32_t *qpl, int32_t n)
     if (!b) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_set_tiles: batch is NULL");
     CtxScope cs_(b->ctx);
     if (!b->bound) return fail(MJK_ERR_STATE, "mjk_batch_set_tiles: batch is not bound");
-    if (int rc = check_qpl(qpl, n, "mjk_batch_set_tiles")) return rc;
+    int units[kTileUnits];
+    if (int rc = check_qpl(qpl, n, "mjk_batch_set_tiles", units)) return rc;
     HIP_TRY(hipSetDevice(b->ctx->device));
     HIP_TRY(hipDeviceSynchronize());  // no launch of this batch may still read the lists
-    for (int q = 0; q < n; ++q) b->qpl[q] = qpl[q];
+    for (int u = 0; u < kTileUnits; ++u) b->qpl[u] = units[u];
     for (auto *p : b->plans) {
-        for (int q = 0; q < n; ++q) p->qpl[q] = qpl[q];
+        for (int u = 0; u < kTileUnits; ++u) p->qpl[u] = units[u];
         rechunk(p, -1);
         if (int rc = upload_work(p, nullptr)) return rc;
     }
@@ -1620,23 +1629,35 @@ int mjk_batch_stats(const mjk_batch *b, mjk_plan_stats *total, int64_t *nq_per_m
 // faster, else halved back (Revert); sweeps repeat while any class improved.
 // Times are the shortest of `reps` launches of that class alone.  J and K
 // hold no meaningful values afterwards.
-int mjk_batch_autotune(mjk_batch *b, const double *D, double *J, double *K, int32_t reps, int32_t *qpl_out,
+int mjk_batch_autotune(mjk_batch *b, const double *D, double *J, double *K, int32_t reps, int32_t *qpl,
                        int32_t n, void *stream)
 {
     if (!b) return fail(MJK_ERR_INVALID_ARG, "mjk_batch_autotune: batch is NULL");
     CtxScope cs_(b->ctx);
     if (!b->bound) return fail(MJK_ERR_STATE, "mjk_batch_autotune: batch is not bound");
-    if (!D || !J || !K || !qpl_out || n != kNumQuartetClasses || reps < 1)
+    if (!D || !J || !K || !qpl || (n != kNumQuartetClasses && n != kTileUnits) || reps < 1)
         return fail(MJK_ERR_INVALID_ARG, "mjk_batch_autotune: bad argument");
+    // entries 0 mark the units to tune (they start at 1); the others are fixed
+    std::vector<int32_t> start(n);
+    std::vector<bool> tune(n);
+    for (int i = 0; i < n; ++i) {
+        tune[i] = qpl[i] == 0;
+        start[i] = tune[i] ? 1 : qpl[i];
+    }
+    int units_now[kTileUnits];
+    if (int rc = check_qpl(start.data(), n, "mjk_batch_autotune", units_now)) return rc;
     HIP_TRY(hipSetDevice(b->ctx->device));
     hipStream_t s = (hipStream_t)stream;
+    const int per = n == kTileUnits ? 1 : kNumKBuckets;  // table entries -> units
     const bool stamps = b->stamps;
     b->stamps = false;
-    std::vector<int32_t> qpl(kNumQuartetClasses, 1);
-    if (int rc = mjk_batch_set_tiles(b, qpl.data(), kNumQuartetClasses)) return rc;
+    std::vector<int32_t> cur(start);
+    if (int rc = mjk_batch_set_tiles(b, cur.data(), n)) return rc;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
+    const bool persistent = (b->plans[0]->opts.flags & MJK_FLAG_PERSISTENT) != 0;
+    // the objective of an entry is the time of its class's launches alone
     auto time_class = [&](int q, double &best) -> int {
         std::vector<Group> sel;
         for (const auto &g : b->groups)
@@ -1646,8 +1667,7 @@ int mjk_batch_autotune(mjk_batch *b, const double *D, double *J, double *K, int3
             HIP_TRY(hipEventRecord(e0, s));
             if (int rc = run_groups(sel, (const JKSeg *)(b->ws + b->o_segs), (uint32_t *)(b->ws + b->o_queue),
                                     (double *)(b->ws + b->o_stage), b->stage_bytes(), b->nslot, D, J, K, nullptr, 0,
-                                    nullptr, s, nullptr, "mjk_batch_autotune",
-                                    (b->plans[0]->opts.flags & MJK_FLAG_PERSISTENT) != 0))
+                                    nullptr, s, nullptr, "mjk_batch_autotune", persistent))
                 return rc;
             HIP_TRY(hipEventRecord(e1, s));
             HIP_TRY(hipEventSynchronize(e1));
@@ -1657,27 +1677,38 @@ int mjk_batch_autotune(mjk_batch *b, const double *D, double *J, double *K, int3
         }
         return MJK_OK;
     };
-    std::vector<int> present;
-    for (const auto &g : b->groups)
-        if (std::find(present.begin(), present.end(), g.qcls) == present.end()) present.push_back(g.qcls);
-    std::vector<bool> done(kNumQuartetClasses, false);
+    // entries to tune that have work: their class has launches (and, per
+    // K-bucket, a bra bin of that bucket with items)
+    std::vector<bool> has_work(n, false);
+    for (const auto *p : b->plans)
+        for (const auto &wl : p->lists) {
+            if (wl.nitems == 0) continue;
+            const BinPair &bp = p->bps[wl.bp];
+            const int e = n == kTileUnits ? bp.qcls * kNumKBuckets + p->bins[bp.X].kb : bp.qcls;
+            has_work[e] = true;
+        }
+    // Algorithm 2: Combine (double the entry's quartets per lane), keep it if
+    // its class got faster, else Revert and retire the entry; sweep while any
+    // entry improved
+    std::vector<bool> done(n, false);
     bool improved = true;
     int rc = MJK_OK;
     while (improved && rc == MJK_OK) {
         improved = false;
-        for (int q : present) {
-            if (done[q] || qpl[q] >= kMaxQpl) continue;
+        for (int i = 0; i < n && rc == MJK_OK; ++i) {
+            if (!tune[i] || !has_work[i] || done[i] || cur[i] >= kMaxQpl) continue;
+            const int q = i * per / kNumKBuckets;
             double t1 = 0.0, t2 = 0.0;
             if ((rc = time_class(q, t1))) break;
-            qpl[q] *= 2;  // Combine
-            if ((rc = mjk_batch_set_tiles(b, qpl.data(), kNumQuartetClasses))) break;
+            cur[i] *= 2;  // Combine
+            if ((rc = mjk_batch_set_tiles(b, cur.data(), n))) break;
             if ((rc = time_class(q, t2))) break;
             if (t2 < t1) {
                 improved = true;
             } else {
-                qpl[q] /= 2;  // Revert
-                done[q] = true;
-                if ((rc = mjk_batch_set_tiles(b, qpl.data(), kNumQuartetClasses))) break;
+                cur[i] /= 2;  // Revert
+                done[i] = true;
+                if ((rc = mjk_batch_set_tiles(b, cur.data(), n))) break;
             }
         }
     }
@@ -1685,8 +1716,10 @@ int mjk_batch_autotune(mjk_batch *b, const double *D, double *J, double *K, int3
     hipEventDestroy(e1);
     b->stamps = stamps;
     if (rc) return rc;
-    for (int q = 0; q < kNumQuartetClasses; ++q) qpl_out[q] = qpl[q];
+    for (int i = 0; i < n; ++i) qpl[i] = cur[i];
     return MJK_OK;
 }
+
+int mjk_num_kbuckets(void) { return kNumKBuckets; }
 
 }  // extern "C"

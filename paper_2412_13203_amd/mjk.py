@@ -13,6 +13,7 @@ calls raise.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -86,7 +87,7 @@ _lib = None
 EXPORTS = ["mjk_lmax", "mjk_grad_lmax", "mjk_num_classes", "mjk_class_l", "mjk_last_error", "mjk_ctx_last_error",
            "mjk_ctx_create", "mjk_ctx_destroy", "mjk_boys",
            "mjk_nbf", "mjk_plan_create", "mjk_plan_bind", "mjk_plan_set_tiles", "mjk_build_jk", "mjk_build_jk_static", "mjk_e2",
-           "mjk_grad_e2", "mjk_e2_backward", "mjk_eri_class", "mjk_schwarz", "mjk_one_electron",
+           "mjk_grad_e2", "mjk_e2_backward", "mjk_eri_class", "mjk_schwarz", "mjk_one_electron", "mjk_num_kbuckets",
            "mjk_plan_set_density_screen", "mjk_plan_stats_get", "mjk_plan_set_timing",
            "mjk_plan_timings", "mjk_plan_destroy",
            "mjk_batch_create", "mjk_batch_bind", "mjk_batch_offsets", "mjk_batch_build_jk", "mjk_batch_set_tiles",
@@ -109,6 +110,7 @@ def lib():
         L.mjk_boys.argtypes = [vp, i32, vp, i64, vp, vp]
         L.mjk_e2_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.mjk_num_classes.restype = ctypes.c_int
+        L.mjk_num_kbuckets.restype = ctypes.c_int
         L.mjk_class_l.argtypes = [i32, ctypes.POINTER(i32)]
         L.mjk_plan_set_tiles.argtypes = [vp, ctypes.POINTER(i32), i32]
         L.mjk_batch_create.argtypes = [vp, i32, ctypes.POINTER(Basis), ctypes.POINTER(JKOpts), ctypes.POINTER(vp),
@@ -148,6 +150,15 @@ def lib():
         L.mjk_plan_destroy.restype = None
         _lib = L
     return _lib
+
+
+def _cache_read(path: str) -> dict:
+    """Autotune tables stored at `path` ({} if the file does not exist)."""
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except FileNotFoundError:
+        return {}
 
 
 def _check(rc):
@@ -331,7 +342,8 @@ class Plan:
         return res
 
     def set_tiles(self, qpl):
-        """Quartets per lane per class (mjk_plan_set_tiles); qpl: sequence of num_classes() ints."""
+        """Quartets per lane (mjk_plan_set_tiles): num_classes() ints, or
+        num_classes() * mjk_num_kbuckets() (per class and bra K-bucket)."""
         arr = (ctypes.c_int32 * len(qpl))(*[int(v) for v in qpl])
         _check(lib().mjk_plan_set_tiles(self._p, arr, len(qpl)))
 
@@ -473,16 +485,62 @@ class Batch:
         arr = (ctypes.c_int32 * len(qpl))(*[int(v) for v in qpl])
         _check(lib().mjk_batch_set_tiles(self._b, arr, len(qpl)))
 
-    def autotune(self, D, reps: int = 2):
-        """Algorithm 2 on this batch; returns the chosen quartets-per-lane table (left active)."""
+    def autotune(self, D, reps: int = 2, per_bucket: bool = True, cache: str | None = None,
+                 key: str | None = None, min_share: float = 0.01, log=None):
+        """Algorithm 2 on this batch (mjk_batch_autotune); returns the chosen
+        quartets-per-lane table (left active): one value per (class, bra
+        K-bucket) with per_bucket, else per class.
+
+        The classes are tuned one call at a time, costliest first (`log`, if
+        given, receives a line per class); classes taking less than
+        `min_share` of one build keep one quartet per lane.  cache: path of a
+        JSON file of tables from earlier runs, keyed by the device
+        architecture, the build's class count, the table layout and `key`
+        (the caller's name for the workload).  A table found there is set
+        without tuning; a new one is added to the file."""
         torch = self.torch
+        nkb = lib().mjk_num_kbuckets() if per_bucket else 1
+        n = num_classes() * nkb
+        ckey = None
+        if cache is not None:
+            arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+            ckey = f"{arch}/classes{num_classes()}/{'class-kbucket' if per_bucket else 'class'}/{key or 'default'}"
+            table = _cache_read(cache).get(ckey)
+            if table is not None and len(table) == n:
+                self.set_tiles(table)
+                return list(table)
         J = torch.empty_like(D)
         K = torch.empty_like(D)
-        n = num_classes()
-        out = (ctypes.c_int32 * n)()
-        _check(lib().mjk_batch_autotune(self._b, self._buf(D, "D"), self._buf(J, "J"), self._buf(K, "K"), int(reps),
-                                        out, n, _stream(torch, self.device)))
-        return [int(out[i]) for i in range(n)]
+        table = [1] * n
+        self.set_tiles(table)
+        self.set_timing(True)
+        self.build_jk(D, J, K)
+        torch.cuda.synchronize(self.device)
+        ms = {t["cls"]: t["ms"] for t in self.timings()}
+        self.set_timing(False)
+        names = class_names()
+        total = sum(ms.values())
+        for q in sorted(range(num_classes()), key=lambda q: -ms.get(names[q], 0.0)):
+            if ms.get(names[q], 0.0) < min_share * total:
+                continue
+            io = list(table)
+            for k in range(nkb):
+                io[q * nkb + k] = 0
+            arr = (ctypes.c_int32 * n)(*io)
+            _check(lib().mjk_batch_autotune(self._b, self._buf(D, "D"), self._buf(J, "J"), self._buf(K, "K"),
+                                            int(reps), arr, n, _stream(torch, self.device)))
+            table = [int(arr[i]) for i in range(n)]
+            if log is not None:
+                log(f"autotune {names[q]} ({ms[names[q]]:.1f} ms at 1 quartet per lane): "
+                    f"{table[q * nkb:(q + 1) * nkb]}")
+        if ckey is not None:
+            entries = _cache_read(cache)
+            entries[ckey] = table
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(entries, fh, indent=1)
+            os.replace(tmp, cache)
+        return table
 
     def set_stamps(self, enable: bool = True):
         _check(lib().mjk_batch_set_stamps(self._b, int(bool(enable))))

@@ -4,6 +4,9 @@ launch per class, with per-class tiles (quartets per lane) from Algorithm 2.
 Each molecule's J and K must equal those of a separate single-molecule plan
 (same kernels, different work split: 1e-12 absolute, summation order only)
 and, for the smallest molecules, the FP64 oracle (1e-10 absolute)."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -83,8 +86,19 @@ def test_autotune_and_stamps():
     J0, K0 = bt.build_jk(D)
     torch.cuda.synchronize()
     J0, K0 = J0.cpu().numpy(), K0.cpu().numpy()
-    qpl = bt.autotune(D, reps=1)
+    nkb = mjk.lib().mjk_num_kbuckets()
+    qpl = bt.autotune(D, reps=1, per_bucket=False)
     assert len(qpl) == mjk.num_classes() and all(v in (1, 2, 4, 8, 16) for v in qpl)
+    # per (class, bra K-bucket), through a cache file: the second call finds
+    # the table there and sets it without tuning
+    import tempfile
+    cache = os.path.join(tempfile.mkdtemp(), "tiles.json")
+    qb = bt.autotune(D, reps=1, per_bucket=True, cache=cache, key="test")
+    assert len(qb) == mjk.num_classes() * nkb and all(v in (1, 2, 4, 8, 16) for v in qb)
+    bt.set_tiles([1] * len(qb))
+    assert bt.autotune(D, reps=1, per_bucket=True, cache=cache, key="test") == qb
+    with open(cache) as fh:
+        assert len(json.load(fh)) == 1
     bt.set_stamps(True)
     J, K = bt.build_jk(D)
     torch.cuda.synchronize()
@@ -105,3 +119,6 @@ def test_batch_rejects_bad_tiles():
         bt.set_tiles([3] * mjk.num_classes())
     with pytest.raises(mjk.MjkError):
         bt.set_tiles([1] * (mjk.num_classes() - 1))
+    with pytest.raises(mjk.MjkError):
+        bt.set_tiles([1] * (mjk.num_classes() * mjk.lib().mjk_num_kbuckets() + 1))
+    bt.set_tiles([2] * (mjk.num_classes() * mjk.lib().mjk_num_kbuckets()))
