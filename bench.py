@@ -249,6 +249,76 @@ def scf_comparison(torch, inputs, dev, config=2, natom=None):
     return out
 
 
+def ablation(torch, mjk, inputs, dev, steps=3):
+    """Component ablation on the 40-atom workload (the paper breaks its gain
+    down by component):
+      * binning by primitive-pair count off (MJK_FLAG_NO_KBINS): the pairs of
+        a class share one bin, so a wave mixes loop trip counts;
+      * Algorithm 1 off: a library whose generator took the fixed textbook
+        recurrence order (build: MJK_FIXED_PATH=1 python -m
+        paper_2412_13203_amd.build --variant fixedpath), timed in a child
+        process of this script;
+      * the two generators' recurrence flops per class (their opcount.json)
+        and the time to construct every class's recurrence path."""
+    import subprocess
+    cfg = inputs.make_config(2)
+    b = cfg["basis"]
+    D = torch.as_tensor(cfg["D"], device=f"cuda:{dev}")
+    out = {"workload": "40-atom s,s,p,d workload as the headline, FP64, per-build times (HIP events)"}
+
+    def time_plan(flags):
+        plan = mjk.Plan(b, tau=cfg["tau"], device=dev, flags=flags)
+        J, K = plan.build_jk(D)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan.build_jk(D, J, K)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps, plan.stats["nquartet_kept"]
+
+    out["full_ms"], nq = time_plan(0)
+    out["no_kbins_ms"], nq2 = time_plan(mjk.FLAG_NO_KBINS)
+    assert nq2 == nq
+    print(f"bench: ablation: full {out['full_ms']:.1f} ms, no K-bins {out['no_kbins_ms']:.1f} ms", file=sys.stderr,
+          flush=True)
+    variant = os.path.join(ROOT, "paper_2412_13203_amd", "_lib", "libmjk_fixedpath.so")
+    if os.path.exists(variant):
+        r = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--steps", str(steps), "--no-mixed",
+                            "--no-grad", "--no-batch", "--no-scf", "--no-cpu-baseline"],
+                           env={**os.environ, "MJK_LIBRARY": variant}, capture_output=True, text=True, timeout=600)
+        if r.returncode == 0:
+            child = json.loads(r.stdout.strip().splitlines()[-1])
+            out["fixed_path_ms"] = child["ms_per_step"]
+            out["fixed_path_classes_ms"] = {k: v["ms_per_step"] for k, v in child["classes"].items()}
+        else:
+            out["fixed_path_error"] = r.stderr[-2000:]
+        print(f"bench: ablation: fixed recurrence order {out.get('fixed_path_ms')} ms", file=sys.stderr, flush=True)
+    flops = {}
+    for tag, sub in (("greedy", "gen"), ("fixed", "gen_fixedpath")):
+        try:
+            recs = json.load(open(os.path.join(ROOT, "paper_2412_13203_amd", "csrc", sub, "opcount.json")))
+        except OSError:
+            continue
+        for rec in recs:
+            if rec.get("forward"):
+                name = "".join("spdf"[l] for l in rec["tuple"])
+                flops.setdefault(name, {})[tag] = {"single_pass": rec["vrr_flops"],
+                                                    "passes": rec.get("split_vrr_flops") or rec["vrr_flops"]}
+    out["vrr_flops_per_primitive_quartet"] = flops
+    sys.path.insert(0, os.path.join(ROOT, "paper_2412_13203_amd", "gen"))
+    import eri_gen
+    for tag, fixed in (("greedy", False), ("fixed", True)):
+        eri_gen.FIXED_PATH = fixed
+        t0 = time.time()
+        for c in eri_gen.quartet_classes(2):
+            eri_gen.best_vrr(*c)
+        out[f"path_construction_s_{tag}"] = time.time() - t0
+    eri_gen.FIXED_PATH = False
+    return out
+
+
 def batch_comparison(torch, mjk, inputs, dev, nmol=64, atom_range=(8, 12), steps=1, tune_reps=1):
     """Many molecules of uneven size: sequential single-molecule FP64 builds
     (default tiles) vs one batch (one launch per class over all molecules),
@@ -385,6 +455,9 @@ def main():
     ap.add_argument("--batch-tune-reps", type=int, default=0,
                     help="builds per autotuner trial (0: no tuning in this run; the batch then uses the "
                          "tiles an earlier autotune run stored for its workload, if any)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="also run the component ablation on the 40-atom workload (binning off, fixed "
+                         "recurrence order if its variant library is built, generator flops)")
     ap.add_argument("--no-scf", action="store_true",
                     help="skip the SCF driver timing (RHF on the 40-atom workload, full and incremental)")
     ap.add_argument("--scf-config", type=int, default=2, help="workload of the SCF timing (2: 40 atoms, 3: 120)")
@@ -521,6 +594,8 @@ def main():
                                         steps=args.batch_steps, tune_reps=args.batch_tune_reps)
     if not args.no_scf:
         out["scf"] = scf_comparison(torch, inputs, dev, config=args.scf_config)
+    if args.ablation:
+        out["ablation"] = ablation(torch, mjk, inputs, dev)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)

@@ -60,6 +60,8 @@ extern "C" {
 #define MJK_FLAG_NO_STAGING 0x4u  /* no staging slots or work counters in the workspace: the plan
                                    * builds J and K with mjk_build_jk_static only (not with
                                    * MJK_FLAG_GRAD, not in batches)                              */
+#define MJK_FLAG_NO_KBINS 0x10u   /* ablation of the binning: shell pairs of one angular-momentum
+                                   * class share one bin whatever their primitive-pair count    */
 #define MJK_FLAG_PERSISTENT 0x8u  /* J/K builds: the per-lane classes run persistent waves that
                                    * take work items from the launch's counter (the split classes
                                    * always do); without it, one block per work item             */

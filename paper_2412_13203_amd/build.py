@@ -33,6 +33,17 @@ HIP_FLAGS = [
 ]
 
 
+def set_variant(name: str | None):
+    """Build into csrc/gen_<name>, _lib/obj_<name>, _lib/libmjk_<name>.so
+    (ablation builds, e.g. MJK_FIXED_PATH=1 ... --variant fixedpath); the
+    default build is untouched."""
+    global GEN, OBJDIR, LIB
+    if name:
+        GEN = os.path.join(CSRC, f"gen_{name}")
+        OBJDIR = os.path.join(LIBDIR, f"obj_{name}")
+        LIB = os.path.join(LIBDIR, f"libmjk_{name}.so")
+
+
 def generate(lmax: int = 3):
     sys.path.insert(0, os.path.join(HERE, "gen"))
     try:
@@ -51,7 +62,10 @@ def generate(lmax: int = 3):
 
 def _compile(src, verbose):
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + HIP_FLAGS + ["-c", "-x", "hip", src, "-o", obj]
+    extra = []
+    if os.path.basename(GEN) != "gen" and os.path.basename(src) == "mjk_host.cpp":
+        extra = [f'-DMJK_GEN_DISPATCH="{os.path.basename(GEN)}/dispatch.inc"']
+    cmd = [HIPCC] + HIP_FLAGS + extra + ["-c", "-x", "hip", src, "-o", obj]
     t0 = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -97,5 +111,7 @@ if __name__ == "__main__":
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--lmax", type=int, default=3)
     ap.add_argument("--out", default=None, help="library path (default: _lib/libmjk.so)")
+    ap.add_argument("--variant", default=None, help="ablation build name (own generated sources, objects, library)")
     args = ap.parse_args()
+    set_variant(args.variant)
     build(jobs=args.jobs, lmax=args.lmax, out=args.out)

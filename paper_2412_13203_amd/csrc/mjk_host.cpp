@@ -26,7 +26,11 @@
 #include <vector>
 
 #include "mjk.h"
-#include "gen/dispatch.inc"
+// generated class table (an ablation build names its own generated directory)
+#ifndef MJK_GEN_DISPATCH
+#define MJK_GEN_DISPATCH "gen/dispatch.inc"
+#endif
+#include MJK_GEN_DISPATCH
 #include "mjk_types.hpp"
 #include "stage_guard.hpp"
 
@@ -625,7 +629,7 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
         return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: schwarz_tau = %g", o.schwarz_tau);
     if (!(std::isfinite(o.fp32_tau) && o.fp32_tau >= 0.0))
         return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: fp32_tau = %g", o.fp32_tau);
-    if (o.flags & ~(MJK_FLAG_CHECK | MJK_FLAG_GRAD | MJK_FLAG_NO_STAGING | MJK_FLAG_PERSISTENT))
+    if (o.flags & ~(MJK_FLAG_CHECK | MJK_FLAG_GRAD | MJK_FLAG_NO_STAGING | MJK_FLAG_PERSISTENT | MJK_FLAG_NO_KBINS))
         return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: unknown flags 0x%x", o.flags);
     if ((o.flags & MJK_FLAG_NO_STAGING) && (in_batch || (o.flags & MJK_FLAG_GRAD)))
         return fail(MJK_ERR_INVALID_ARG, "mjk_plan_create: MJK_FLAG_NO_STAGING is for single J/K plans only");
@@ -690,7 +694,7 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
     std::vector<int> bin_size(kNumPairClasses * kNumKBuckets, 0);
     std::vector<std::vector<int32_t>> bin_first(kNumPairClasses * kNumKBuckets);
     for (const auto &sp : p->pairs_nat) {
-        const int key = sp.cls * kNumKBuckets + kbucket(sp.nprim);
+        const int key = sp.cls * kNumKBuckets + ((o.flags & MJK_FLAG_NO_KBINS) ? 0 : kbucket(sp.nprim));
         bin_size[key]++;
         bin_first[key].push_back(sp.A);
     }
@@ -1017,7 +1021,9 @@ static int plan_bind(mjk_plan *p, void *workspace, size_t bytes, hipStream_t s)
     for (int k = 0; k < p->npair; ++k) p->sorted[k] = k;
     std::stable_sort(p->sorted.begin(), p->sorted.end(), [&](int x, int y) {
         const ShellPairD &a = p->pairs_nat[x], &b = p->pairs_nat[y];
-        const int ka = a.cls * kNumKBuckets + kbucket(a.nprim), kb = b.cls * kNumKBuckets + kbucket(b.nprim);
+        const bool kbins = !(p->opts.flags & MJK_FLAG_NO_KBINS);
+        const int ka = a.cls * kNumKBuckets + (kbins ? kbucket(a.nprim) : 0),
+                  kb = b.cls * kNumKBuckets + (kbins ? kbucket(b.nprim) : 0);
         if (ka != kb) return ka < kb;
         if (a.A != b.A) return a.A < b.A;
         if (a.Q != b.Q) return a.Q > b.Q;

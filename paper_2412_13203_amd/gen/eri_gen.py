@@ -132,6 +132,18 @@ class VRR:
             node = VNode(e, f, m, name=f"F[{m}]")
             self.nodes[key] = node
             return node
+        if FIXED_PATH:
+            # ablation: the textbook order, no search (ket first, then bra,
+            # along the first axis with a non-zero exponent)
+            side, t = ("k", f) if f != ZERO3 else ("b", e)
+            i = next(j for j in range(3) if t[j] > 0)
+            ch = self._children(e, f, m, side, i)
+            deps = {k: self.need(*c) for k, c in ch.items()}
+            node = VNode(e, f, m, side=side, axis=i, deps=deps)
+            node.name = f"v{len(self.order)}"
+            self.nodes[key] = node
+            self.order.append(node)
+            return node
         # Algorithm 1: score every position, keep the cheapest
         best = None
         for side, t in (("b", e), ("k", f)):
@@ -188,6 +200,9 @@ class VRR:
 
 
 LAMBDAS = (0.0, 0.5, 1.0, 2.0, 4.0)
+# MJK_FIXED_PATH=1 (ablation of Algorithm 1): every node takes the fixed
+# textbook step instead of the greedy choice
+FIXED_PATH = os.environ.get("MJK_FIXED_PATH") == "1"
 
 
 def schedule_low_pressure(order):
@@ -236,7 +251,7 @@ def schedule_low_pressure(order):
 
 def best_vrr(la, lb, lc, ld, targets=None):
     best = None
-    for lam in LAMBDAS:
+    for lam in ((0.0,) if FIXED_PATH else LAMBDAS):
         v = VRR(la, lb, lc, ld, lam)
         v.build(targets)
         key = (v.flops(), len(v.order))

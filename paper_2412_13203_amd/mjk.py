@@ -29,6 +29,7 @@ FLAG_CHECK = 0x1
 FLAG_GRAD = 0x2
 FLAG_NO_STAGING = 0x4
 FLAG_PERSISTENT = 0x8
+FLAG_NO_KBINS = 0x10
 
 
 class MjkError(RuntimeError):
