@@ -283,6 +283,17 @@ def ablation(torch, mjk, inputs, dev, steps=3):
     assert nq2 == nq
     print(f"bench: ablation: full {out['full_ms']:.1f} ms, no K-bins {out['no_kbins_ms']:.1f} ms", file=sys.stderr,
           flush=True)
+    # every pair of the 40-atom workload has K_A K_B = 9, so the binning by
+    # primitive count only matters where K varies: a 32-atom molecule of the
+    # batched recipe (s, s, p, d shells, K ~ U{1..6})
+    m = inputs.make_batch(nmol=1, seed=4, atom_range=(32, 32), shells=(0, 0, 1, 2))[0]
+    b, D = m["basis"], torch.as_tensor(m["D"], device=f"cuda:{dev}")
+    out["varK_workload"] = f"32-atom molecule of the batched recipe, s,s,p,d, K ~ U{{1..6}}, nbf {b['nbf']}"
+    out["varK_full_ms"], nq = time_plan(0)
+    out["varK_no_kbins_ms"], nq2 = time_plan(mjk.FLAG_NO_KBINS)
+    assert nq2 == nq
+    print(f"bench: ablation (K ~ U{{1..6}}): full {out['varK_full_ms']:.1f} ms, no K-bins "
+          f"{out['varK_no_kbins_ms']:.1f} ms", file=sys.stderr, flush=True)
     variant = os.path.join(ROOT, "paper_2412_13203_amd", "_lib", "libmjk_fixedpath.so")
     if os.path.exists(variant):
         r = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--steps", str(steps), "--no-mixed",
