@@ -3,12 +3,14 @@
     python -m paper_2412_13203_amd.build [--jobs N] [--lmax L]
 
 Produces paper_2412_13203_amd/_lib/libmjk.so (in-tree; loaded by the
-Python binding).  Every call regenerates and recompiles.
+Python binding).  Every call recompiles; the generated sources are rewritten
+when the generator, lmax or its MJK_* switches changed.
 """
 from __future__ import annotations
 
 import argparse
 import glob
+import hashlib
 import os
 import shutil
 import subprocess
@@ -44,7 +46,32 @@ def set_variant(name: str | None):
         LIB = os.path.join(LIBDIR, f"libmjk_{name}.so")
 
 
-def generate(lmax: int = 3):
+def _generator_stamp(lmax: int) -> str:
+    """Hash of what the generated sources depend on: the generator scripts,
+    lmax and the generator's environment switches."""
+    h = hashlib.sha256()
+    for f in ("eri_gen.py", "boys_gen.py"):
+        with open(os.path.join(HERE, "gen", f), "rb") as fh:
+            h.update(fh.read())
+    h.update(f"lmax={lmax}".encode())
+    for k in ("MJK_MAX_ACC", "MJK_GRAD_MAX_ACC", "MJK_GRAD_MAX_ACC_LOW_L", "MJK_FIXED_PATH", "MJK_NO_SCHED",
+              "MJK_PASS_SEARCH", "MJK_SCHED_WINDOW"):
+        h.update(f"{k}={os.environ.get(k, '')}".encode())
+    return h.hexdigest()
+
+
+def generate(lmax: int = 3, verbose: bool = False):
+    """Write the per-class sources into GEN.  The generator is deterministic
+    (seeded pass search), so sources whose stamp matches the generator and
+    its inputs are kept instead of regenerated (the pass search for the f
+    classes takes minutes); the compile always runs."""
+    stamp = _generator_stamp(lmax)
+    stamp_file = os.path.join(GEN, ".stamp")
+    tus = sorted(glob.glob(os.path.join(GEN, "tu_*.hip")))
+    if tus and os.path.exists(stamp_file) and open(stamp_file).read().strip() == stamp:
+        if verbose:
+            print(f"  generated sources up to date ({len(tus)} units)", flush=True)
+        return tus
     sys.path.insert(0, os.path.join(HERE, "gen"))
     try:
         import boys_gen
@@ -52,11 +79,13 @@ def generate(lmax: int = 3):
     finally:
         sys.path.pop(0)
     if os.path.isdir(GEN):
-        for pat in ("tu_*.hip", "cls_*.inc", "eri_classes.inc"):
+        for pat in ("tu_*.hip", "cls_*.inc", "eri_classes.inc", ".stamp"):
             for f in glob.glob(os.path.join(GEN, pat)):
                 os.remove(f)
     boys_gen.generate(GEN)
     _, tus = eri_gen.generate(GEN, lmax)
+    with open(stamp_file, "w") as fh:
+        fh.write(stamp + "\n")
     return tus
 
 
@@ -77,7 +106,7 @@ def _compile(src, verbose):
 
 def build(verbose: bool = True, jobs: int | None = None, lmax: int = 3, out: str | None = None) -> str:
     t0 = time.time()
-    tus = generate(lmax)
+    tus = generate(lmax, verbose)
     if os.path.isdir(OBJDIR):
         shutil.rmtree(OBJDIR)
     os.makedirs(OBJDIR, exist_ok=True)
