@@ -102,8 +102,14 @@ def cpu_baseline(cfg, nbra=32):
     t0 = time.time()
     _, _, nq = oracle.jk_rows(b, D, tau, rows, Q)
     dt = time.time() - t0
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {
-        "value": nq / dt, "unit": "quartets/s", "cores": oracle.nthreads(), "kind": "oracle",
+        "value": nq / dt, "unit": "quartets/s", "cores": oracle.nthreads(), "cpu_model": cpu, "kind": "oracle",
         "sample": f"{len(rows)} bra pairs (every {stride}th of {npair}), all kept kets: {nq} quartets in "
                   f"{dt:.2f} s; Schwarz table {t_q:.2f} s not included",
     }
