@@ -966,16 +966,19 @@ __device__ __forceinline__ void jk_split_body(const JKLaunch &a)
     }
 }
 
-// Passes of one quartet with its primitive quartets spread over the wave
-// (the contraction of Eq. 2 summed across the lanes): pass P's targets go to
-// positions split_off<P> + j of the quartet's slot `sq` (pass order).
-// The sums over the lanes go through the 16 x 65 LDS buffer s_tr (16
-// accumulators at a time, each summed by one lane in a fixed order), which
-// keeps the code small and the result independent of timing.
+// Phase 1 of the split eri kernel, one code path for both forms (the pass
+// code is instantiated once): each lane sums the primitive quartets
+// ip = pstart, pstart + pstep, ... of its quartet (bra, ket).  reduce = false:
+// one quartet per lane, its sums stored quartet-major as in the J/K kernel.
+// reduce = true: the wave's lanes share one quartet (pstart = lane,
+// pstep = 64, the contraction of Eq. 2 spread over the wave) and their sums
+// are added through the 16 x 65 LDS buffer s_tr, 16 accumulators at a time,
+// each by one lane in a fixed order, and stored as quartet 0 of the slot.
 template <int LA, int LB, int LC, int LD, int P, typename T>
-__device__ __forceinline__ void split_passes_prim(const ShellPairD &bra, const ShellPairD &ket,
-                                                  const PrimPairD *__restrict__ prims, double *__restrict__ sq,
-                                                  int lane, double *__restrict__ s_tr)
+__device__ __forceinline__ void eri_passes(const ShellPairD &bra, const ShellPairD &ket,
+                                           const PrimPairD *__restrict__ prims, bool active,
+                                           double *__restrict__ stage, int lane, double *__restrict__ s_tr,
+                                           int pstart, int pstep, bool reduce)
 {
     using S = EriSplit<LA, LB, LC, LD>;
     if constexpr (P < S::NPASS) {
@@ -984,8 +987,8 @@ __device__ __forceinline__ void split_passes_prim(const ShellPairD &bra, const S
         T acc[NP];
 #pragma unroll
         for (int i = 0; i < NP; ++i) acc[i] = T(0);
-        const int nb = bra.nprim, npq = nb * ket.nprim;
-        for (int ip = lane; ip < npq; ip += 64) {
+        const int nb = bra.nprim, npq = active ? nb * ket.nprim : 0;
+        for (int ip = pstart; ip < npq; ip += pstep) {
             const PrimPairD kp = load_prim(prims + ket.prim_off + ip / nb);
             const PrimPairD bp = load_prim(prims + bra.prim_off + ip % nb);
             VrrGeom<double> g;
@@ -1006,20 +1009,42 @@ __device__ __forceinline__ void split_passes_prim(const ShellPairD &bra, const S
                 S::template vrr<P, T>(Ft, h, acc);
             }
         }
+        if (reduce) {
 #pragma unroll
-        for (int c0 = 0; c0 < NP; c0 += 16) {
+            for (int c0 = 0; c0 < NP; c0 += 16) {
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if (c0 + j < NP) s_tr[j * 65 + lane] = (double)acc[c0 + j];
-            __syncthreads();
-            if (lane < 16 && c0 + lane < NP) {
-                double v = 0.0;
-                for (int l = 0; l < 64; ++l) v += s_tr[lane * 65 + l];
-                sq[O + c0 + lane] = v;
+                for (int j = 0; j < 16; ++j)
+                    if (c0 + j < NP) s_tr[j * 65 + lane] = (double)acc[c0 + j];
+                __syncthreads();
+                if (lane < 16 && c0 + lane < NP) {
+                    double v = 0.0;
+                    for (int l = 0; l < 64; ++l) v += s_tr[lane * 65 + l];
+                    stage[O + c0 + lane] = v;
+                }
+                __syncthreads();
             }
-            __syncthreads();
+        } else {
+            // quartet-major store through the transpose, as split_pass does
+            const int jj = lane & 15;
+            int qo = (lane >> 4) * S::NACC + O + jj, to = jj * 65 + (lane >> 4), lo = lane;
+            __asm__ volatile("" : "+v"(qo), "+v"(to), "+v"(lo));
+            double *sq = stage + qo;
+            const double *tr = s_tr + to;
+            double *tw = s_tr + lo;
+#pragma unroll
+            for (int c0 = 0; c0 < NP; c0 += 16) {
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if (c0 + j < NP) tw[j * 65] = (double)acc[c0 + j];
+                __syncthreads();
+                if (c0 + jj < NP) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) sq[4 * r * S::NACC + c0] = tr[4 * r];
+                }
+                __syncthreads();
+            }
         }
-        split_passes_prim<LA, LB, LC, LD, P + 1, T>(bra, ket, prims, sq, lane, s_tr);
+        eri_passes<LA, LB, LC, LD, P + 1, T>(bra, ket, prims, active, stage, lane, s_tr, pstart, pstep, reduce);
     }
 }
 
@@ -1027,9 +1052,8 @@ __device__ __forceinline__ void split_passes_prim(const ShellPairD &bra, const S
 // Explicit ERI blocks (and Schwarz factors) of classes split into recurrence
 // passes: persistent blocks take 64 requested quartets at a time; phase 1 as
 // in the split J/K kernel (one quartet per lane, passes into the block's
-// staging slot), or, with `deconstruct` (classes up to L = 9), one quartet at
-// a time with its primitive quartets spread over the lanes; phase 2 one
-// quartet at a time: bra HRR one ket column per
+// staging slot), or, with `deconstruct`, one quartet at a time with its
+// primitive quartets spread over the lanes; phase 2 one quartet at a time: bra HRR one ket column per
 // lane, ket HRR one (ab) row per lane, then the block written in the
 // caller's shell order, or, in Schwarz mode (a.Q set, items (pair, pair)),
 // Q = sqrt(max_{a,b} (ab|ab)) written for the pair.
@@ -1047,27 +1071,17 @@ __global__ __launch_bounds__(64) void k_eri_split(EriLaunch a)
     static_assert(split_off<LA, LB, LC, LD, S::NPASS>() == NACC, "passes must partition the targets");
     const int lane = threadIdx.x;
     double *stage = a.stage + (size_t)blockIdx.x * NACC * 64;
-    // the deconstructed form doubles the pass code of the kernel; above
-    // L = 9 ((ff|dd), (fd|fd), (ff|fp) and up) it would take most of the
-    // build's compile time, so those classes always use one quartet per lane
-    constexpr bool DECON = LA + LB + LC + LD <= 9;
-    const bool decon = DECON && a.deconstruct;
+    const bool decon = a.deconstruct != 0;
     const int gsize = decon ? 1 : 64;  // quartets per group
     const int ngroup = (a.n + gsize - 1) / gsize;
     for (int grp = blockIdx.x; grp < ngroup; grp += gridDim.x) {
         const int t0 = grp * gsize;
         const int nact = min(a.n - t0, gsize);
-        if (decon) {
-            if constexpr (DECON) {
-                const EriItem it = a.items[t0];
-                split_passes_prim<LA, LB, LC, LD, 0, T>(a.pairs[it.bra], a.pairs[it.ket], a.prims, stage, lane, s_tr);
-            }
-        } else {
-            const bool active = lane < nact;
-            const EriItem it = a.items[t0 + (active ? lane : 0)];
-            const ShellPairD bra = a.pairs[it.bra];
-            const ShellPairD ket = a.pairs[it.ket];
-            split_passes<LA, LB, LC, LD, 0, T, WK_ONE, true>(bra, ket, a.prims, active, stage, lane, s_tr);
+        {
+            const bool active = decon || lane < nact;
+            const EriItem it = a.items[t0 + (decon || !active ? 0 : lane)];
+            eri_passes<LA, LB, LC, LD, 0, T>(a.pairs[it.bra], a.pairs[it.ket], a.prims, active, stage, lane, s_tr,
+                                            decon ? lane : 0, decon ? 64 : 1, decon);
         }
         __syncthreads();
         for (int q = 0; q < nact; ++q) {
@@ -1198,7 +1212,7 @@ int launch_eri_split(const EriLaunch &a, hipStream_t s)
         grid_cache = occupancy_grid(k_eri_split<LA, LB, LC, LD, T>, 0);
         if (grid_cache <= 0) return kLaunchHip;
     }
-    const int64_t groups = (LA + LB + LC + LD <= 9 && a.deconstruct) ? a.n : (a.n + 63) / 64;
+    const int64_t groups = a.deconstruct ? a.n : (a.n + 63) / 64;
     const int64_t grid = persistent_blocks(grid_cache, a.nslot, groups, true);
     if (grid < 1 || !staging_fits(grid, (int64_t)EriSplit<LA, LB, LC, LD>::NACC * 64, a.stage_bytes))
         return kLaunchStaging;
