@@ -22,11 +22,14 @@ J(D_n) = J(D_{n-1}) + J(D_n - D_{n-1}) (J and K are linear in D), with the
 screening of each difference build weighted by the difference itself: a
 quartet is skipped when its Schwarz bound times the largest element of the
 difference density in the shell rows it touches is below `inc_tau` (default
-the plan's Schwarz threshold / 100; `mjk_plan_set_density_screen`).  Every `rebuild_every` iterations
-(and in the first) the full J and K are rebuilt, which bounds the drift, and
-an iteration that meets the convergence test on an incremental build is
-repeated with a full build of the same density before the loop stops (when
-that full build does not confirm it, the rest of the run builds in full).
+the plan's Schwarz threshold; `mjk_plan_set_density_screen`).  Every
+`rebuild_every` iterations (and in the first) the full J and K are rebuilt,
+which bounds the drift; iterations whose density changes by more than
+`inc_start` anywhere build in full (the screen would keep nearly every
+quartet); once the largest commutator element is within 10x of `err_tol`
+the run finishes with full builds, and an iteration that meets the
+convergence test on an incremental build is repeated with a full build of
+the same density before the loop stops.
 """
 from __future__ import annotations
 
@@ -73,7 +76,8 @@ class RHF:
         return 0.5 * (D + D.T), e
 
     def run(self, max_iter: int = 100, e_tol: float = 1e-10, err_tol: float = 1e-8, ndiis: int = 8, D0=None,
-            incremental: bool = False, rebuild_every: int = 8, inc_tau: float | None = None, log=None) -> dict:
+            incremental: bool = False, rebuild_every: int = 8, inc_tau: float | None = None,
+            inc_start: float = 1e-2, log=None) -> dict:
         torch = self.torch
         stream = torch.cuda.current_stream(self.dev)
         D = self.density(self.H)[0] if D0 is None else torch.as_tensor(D0, dtype=torch.float64, device=self.dev)
@@ -85,16 +89,20 @@ class RHF:
         focks, errs = [], []
         energies, t_iter, t_jk, kept, was_full = [], [], [], [], []
         e_old, converged, it, confirm, inc_off = None, False, 0, False, False
-        inc_tau = self.plan.tau * 1e-2 if inc_tau is None else inc_tau
+        inc_tau = self.plan.tau if inc_tau is None else inc_tau
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         for it in range(1, max_iter + 1):
             ev[0].record(stream)
             full = not incremental or inc_off or D_prev is None or confirm or (it - 1) % rebuild_every == 0
+            if not full:
+                dD = D - D_prev
+                # while the density still moves by more than inc_start the
+                # screen would keep nearly every quartet: build in full
+                full = float(dD.abs().max()) > inc_start
             if full:
                 self.plan.set_density_screen(None)
                 self.plan.build_jk(D, J, K)
             else:
-                dD = D - D_prev
                 self.plan.set_density_screen(dD, inc_tau)
                 self.plan.build_jk(dD, dJ, dK)
                 J += dJ
@@ -114,6 +122,10 @@ class RHF:
             # it, the screening noise is at the convergence threshold and the
             # remaining iterations build J and K in full
             if confirm and not done:
+                inc_off = True
+            # near convergence the screening noise is of the size of the
+            # remaining error: finish with full builds
+            if emax < 10.0 * err_tol:
                 inc_off = True
             confirm = done and not full
             if not done:
