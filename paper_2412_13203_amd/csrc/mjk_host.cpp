@@ -17,12 +17,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "mjk.h"
@@ -796,6 +799,18 @@ static int plan_create(mjk_ctx *ctx, const mjk_basis *b, const mjk_jk_opts *opts
     return MJK_OK;
 }
 
+// host threads for the planner's per-bin-pair loops: the hardware threads,
+// capped by OMP_NUM_THREADS when set and at 16
+static size_t host_threads()
+{
+    size_t n = std::max(1u, std::thread::hardware_concurrency());
+    if (const char *e = std::getenv("OMP_NUM_THREADS")) {
+        const long v = std::strtol(e, nullptr, 10);
+        if (v > 0) n = std::min(n, (size_t)v);
+    }
+    return std::min<size_t>(n, 16);
+}
+
 // tables, Schwarz factors, sort and work lists of one plan (its workspace)
 // Stage 2 of the plan: per bin pair, per bra, the kept prefix of every run of
 // the ket bin as kept-run records, the work lists' chunking, the launch groups
@@ -813,7 +828,6 @@ static int build_lists(mjk_plan *p, const double *shell_w, double tau_w, hipStre
     char *w = p->ws;
     p->work.assign(p->work_ints, 0);
     std::vector<KetRun> runs;
-    runs.reserve(p->max_runs);
     int64_t nq_kept = 0, nprimq = 0, ncart = 0, nq32 = 0;
     double flops = 0.0, gflops = 0.0;
     // kets of [lo, lo + n) (bin positions of Y, Q descending) with qb * Q >= thr
@@ -828,7 +842,6 @@ static int build_lists(mjk_plan *p, const double *shell_w, double tau_w, hipStre
         }
         return a0;
     };
-    std::vector<KetRun> r32;
     // per run of every bin: max(w_C, max over its kets of w_D)
     std::vector<std::vector<double>> run_w;
     if (shell_w) {
@@ -842,8 +855,17 @@ static int build_lists(mjk_plan *p, const double *shell_w, double tau_w, hipStre
             }
         }
     }
-    for (size_t il = 0; il < p->lists.size(); il += 2) {
-        WorkList &l64 = p->lists[il], &l32 = p->lists[il + 1];
+    // the bin pairs are independent: each fills its own counts and run
+    // offsets (relative to its own records) on a host thread, then the
+    // records are concatenated in list order, which fixes the layout
+    struct ListRuns {
+        std::vector<KetRun> r64, r32;
+        int64_t q64 = 0, q32 = 0, pq64 = 0, pq32 = 0;
+    };
+    const size_t npl = p->lists.size() / 2;
+    std::vector<ListRuns> lr(npl);
+    auto fill_list = [&](size_t ip) {
+        WorkList &l64 = p->lists[2 * ip], &l32 = p->lists[2 * ip + 1];
         const BinPair &bp = p->bps[l64.bp];
         const Bin &X = p->bins[bp.X], &Y = p->bins[bp.Y];
         const auto &yr = bin_runs[bp.Y];
@@ -853,13 +875,12 @@ static int build_lists(mjk_plan *p, const double *shell_w, double tau_w, hipStre
         int32_t *c32 = p->work.data() + l32.off, *rb32 = c32 + X.count;
         std::vector<int64_t> ynp(Y.count + 1, 0);  // prefix of K_C K_D over the ket bin
         for (int k = 0; k < Y.count; ++k) ynp[k + 1] = ynp[k] + psort[Y.begin + k].nprim;
-        r32.clear();
-        int64_t q64 = 0, q32 = 0, pq64 = 0, pq32 = 0;
+        ListRuns &o = lr[ip];
         for (int b = 0; b < X.count; ++b) {
             const double qb = psort[X.begin + b].Q;
             const int64_t nb = psort[X.begin + b].nprim;
-            rb64[b] = (int32_t)runs.size();
-            rb32[b] = (int32_t)r32.size();
+            rb64[b] = (int32_t)o.r64.size();
+            rb32[b] = (int32_t)o.r32.size();
             int n64 = 0, n32 = 0;
             const double wb = shell_w ? std::max(shell_w[psort[X.begin + b].A], shell_w[psort[X.begin + b].B]) : 0.0;
             for (size_t ri = 0; ri < yr.size(); ++ri) {
@@ -874,27 +895,65 @@ static int build_lists(mjk_plan *p, const double *shell_w, double tau_w, hipStre
                 if (shell_w) keep = kept_len(Y, run.first, keep, qb * std::max(wb, run_w[bp.Y][ri]), tau_w);
                 const int k64 = t32 > 0.0 ? std::min(keep, kept_len(Y, run.first, keep, qb, t32)) : keep;
                 if (k64 > 0) {
-                    runs.push_back({n64, run.first});
+                    o.r64.push_back({n64, run.first});
                     n64 += k64;
-                    pq64 += nb * (ynp[run.first + k64] - ynp[run.first]);
+                    o.pq64 += nb * (ynp[run.first + k64] - ynp[run.first]);
                 }
                 if (keep > k64) {
-                    r32.push_back({n32, run.first + k64});
+                    o.r32.push_back({n32, run.first + k64});
                     n32 += keep - k64;
-                    pq32 += nb * (ynp[run.first + keep] - ynp[run.first + k64]);
+                    o.pq32 += nb * (ynp[run.first + keep] - ynp[run.first + k64]);
                 }
             }
             c64[b] = n64;
             c32[b] = n32;
-            q64 += n64;
-            q32 += n32;
+            o.q64 += n64;
+            o.q32 += n32;
         }
-        rb64[X.count] = (int32_t)runs.size();
-        rb32[X.count] = (int32_t)r32.size();
-        const int32_t base32 = (int32_t)runs.size();
-        for (int b = 0; b <= X.count; ++b) rb32[b] += base32;
-        runs.insert(runs.end(), r32.begin(), r32.end());
-        if (runs.size() > p->max_runs) return fail(MJK_ERR_STATE, "mjk_plan_bind: kept-run records exceed their bound");
+        rb64[X.count] = (int32_t)o.r64.size();
+        rb32[X.count] = (int32_t)o.r32.size();
+    };
+    {
+        std::atomic<size_t> next{0};
+        std::atomic<bool> failed{false};
+        auto worker = [&]() {
+            try {
+                for (size_t ip; (ip = next.fetch_add(1)) < npl && !failed.load();) fill_list(ip);
+            } catch (...) {
+                failed = true;
+            }
+        };
+        const int nth = (int)std::min<size_t>(host_threads(), std::max<size_t>(npl, 1));
+        std::vector<std::thread> pool;
+        try {
+            for (int t = 1; t < nth; ++t) pool.emplace_back(worker);
+        } catch (...) {  // fewer threads: the others take the remaining lists
+        }
+        worker();
+        for (auto &t : pool) t.join();
+        if (failed) return fail(MJK_ERR_UNSUPPORTED, "mjk_plan_bind: host memory exhausted by the kept-run records");
+    }
+    size_t nruns = 0;
+    for (const auto &o : lr) nruns += o.r64.size() + o.r32.size();
+    if (nruns > p->max_runs) return fail(MJK_ERR_STATE, "mjk_plan_bind: kept-run records exceed their bound");
+    runs.reserve(nruns);
+    for (size_t il = 0; il < p->lists.size(); il += 2) {
+        WorkList &l64 = p->lists[il], &l32 = p->lists[il + 1];
+        const BinPair &bp = p->bps[l64.bp];
+        const Bin &X = p->bins[bp.X];
+        const ClassEntry &ce = kClassTable[bp.qcls];
+        int32_t *rb64 = p->work.data() + l64.off + X.count, *rb32 = p->work.data() + l32.off + X.count;
+        ListRuns &o = lr[il / 2];
+        const int32_t base64 = (int32_t)runs.size(), base32 = (int32_t)(runs.size() + o.r64.size());
+        for (int b = 0; b <= X.count; ++b) {
+            rb64[b] += base64;
+            rb32[b] += base32;
+        }
+        runs.insert(runs.end(), o.r64.begin(), o.r64.end());
+        runs.insert(runs.end(), o.r32.begin(), o.r32.end());
+        std::vector<KetRun>().swap(o.r64);
+        std::vector<KetRun>().swap(o.r32);
+        const int64_t q64 = o.q64, q32 = o.q32, pq64 = o.pq64, pq32 = o.pq32;
         const int nout = ncart_h(ce.la) * ncart_h(ce.lb) * ncart_h(ce.lc) * ncart_h(ce.ld);
         const int L = ce.la + ce.lb + ce.lc + ce.ld;
         const double fpq = ce.vrr_flops + prim_overhead_flops(L), fq = ce.hrr_flops + 12.0 * nout;
