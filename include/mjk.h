@@ -157,8 +157,11 @@ int mjk_plan_create(mjk_ctx *ctx, const mjk_basis *basis, const mjk_jk_opts *opt
  * class-sorted pair order and the quartet work lists (Section 5: pairs
  * sorted by angular momentum and tiled within a class; quartet blocks are
  * formed from pair tiles).  Synchronizes `stream` once (the Schwarz factors
- * come back to the host for the sort).  The workspace must stay allocated
- * and untouched until mjk_plan_destroy or the next bind. */
+ * come back to the host for the sort).  The work lists are built on up to
+ * 16 host threads (fewer if OMP_NUM_THREADS says so), one bin pair at a
+ * time per thread; their layout does not depend on the thread count.  The
+ * workspace must stay allocated and untouched until mjk_plan_destroy or the
+ * next bind. */
 int mjk_plan_bind(mjk_plan *plan, void *workspace, size_t bytes, void *stream);
 
 /* J and K for density D (nbf x nbf, symmetric), both overwritten.
@@ -257,7 +260,9 @@ int mjk_eri_class(mjk_plan *plan, const int32_t *quartets, int64_t nq, double *o
  * quartet's J and K updates read: each contribution is at most
  * |(ab|cd)| max |dD| over those blocks).  dD = NULL restores the plain lists.
  * The screen stays in force for every later mjk_build_jk of the plan.
- * Synchronizes the device (host rebuild of the lists, then an upload). */
+ * Synchronizes the device (host rebuild of the lists on the threads
+ * mjk_plan_bind uses, then an upload).  MJK_ERR_UNSUPPORTED if host memory
+ * runs out for the lists (mjk_plan_bind alike). */
 int mjk_plan_set_density_screen(mjk_plan *plan, const double *dD, double tau, void *stream);
 
 /* One-electron matrices of the SCF iteration (Section 2.1: the Fock matrix
