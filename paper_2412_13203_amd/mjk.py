@@ -363,10 +363,13 @@ class Plan:
         """Density-weighted screening by the density change dD (contiguous
         float64 (nbf, nbf) on the plan's device) at threshold tau (default:
         the plan's Schwarz threshold), or dD = None to restore the plain work
-        lists (mjk_plan_set_density_screen)."""
+        lists (mjk_plan_set_density_screen); `stats` follows the new lists."""
         ptr = self._dev_matrix(dD, "dD") if dD is not None else ctypes.c_void_p()
         t = self.tau if tau is None else float(tau)
         _check(lib().mjk_plan_set_density_screen(self._p, ptr, ctypes.c_double(t), _stream(self.torch, self.device)))
+        st = PlanStats()
+        _check(lib().mjk_plan_stats_get(self._p, ctypes.byref(st)))
+        self.stats = st.as_dict()
 
     def kept_quartets(self) -> int:
         """Unique shell quartets the current work lists run."""

@@ -12,6 +12,8 @@ at every iteration), through the C ABI:
     more quartets than the Schwarz screen, keeps them all for a density change
     of 1 in every row, drops quartets for a small one with a J/K error inside the
     skipped bound, and None restores the plain lists exactly;
+  * the work lists do not depend on the number of host threads that build
+    them;
   * the incremental SCF (difference densities with that screening) converges
     to the energy of the full builds.
 """
@@ -152,6 +154,41 @@ def test_density_screen_bounds_and_restores():
     J2, K2 = plan.build_jk(D)
     torch.cuda.synchronize()
     assert float((J2 - J0).abs().max()) <= 1e-12 and float((K2 - K0).abs().max()) <= 1e-12
+
+
+def test_work_lists_do_not_depend_on_host_threads(monkeypatch):
+    """The planner builds the work lists of the bin pairs on host threads;
+    one thread and the default count give the same lists (kept counts,
+    primitive quartets, FP32 split) and the same J and K, for the Schwarz
+    lists and for a density-weighted screen."""
+    torch, mjk, inputs, _ = _mods()
+    cfg = inputs.make_config(2, natom=8)
+    b = cfg["basis"]
+    D = torch.as_tensor(cfg["D"], device="cuda:0")
+    rng = np.random.default_rng(8)
+    E = rng.standard_normal(D.shape) * 1e-6
+    dD = torch.as_tensor(0.5 * (E + E.T), device="cuda:0")
+    keys = ("nquartet_kept", "nquartet_fp32", "nprim_quartet_kept", "ncart_eri_kept")
+    res = []
+    for threads in ("1", None):
+        if threads is None:
+            monkeypatch.delenv("OMP_NUM_THREADS", raising=False)
+        else:
+            monkeypatch.setenv("OMP_NUM_THREADS", threads)
+        plan = mjk.Plan(b, tau=1e-10, fp32_tau=1e-7)
+        st = tuple(plan.stats[k] for k in keys)
+        J, K = plan.build_jk(D)
+        plan.set_density_screen(dD)
+        st_d = tuple(plan.stats[k] for k in keys)
+        Jd, Kd = plan.build_jk(dD)
+        torch.cuda.synchronize()
+        res.append((st, st_d, J, K, Jd, Kd))
+    (a, ad, *ma), (c, cd, *mc) = res
+    print(f"  one thread vs default: {a} / {ad}", flush=True)
+    assert a == c and ad == cd
+    assert a[1] > 0 and ad[0] < a[0]
+    for x, y in zip(ma, mc):
+        assert float((x - y).abs().max()) <= 1e-12
 
 
 def test_incremental_rhf_matches_full():
