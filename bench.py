@@ -485,9 +485,9 @@ def main():
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
               "the J/K work would shard by class-pair tiles with one all-reduce of J and K, "
-              "which is not built here.", file=sys.stderr)
+              "which is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch

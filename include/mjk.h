@@ -16,7 +16,7 @@
  *
  * Conventions shared by every call:
  *   - Units are bohr.  Real Cartesian functions, chemists' notation.
- *   - Shells: l in 0..mjk_lmax() (3 in this build), 1..6 primitives.  The
+ *   - Shells: l in 0..mjk_lmax() (3 in the default build), 1..6 primitives.  The
  *     nuclear gradient takes l <= mjk_grad_lmax().  Coefficients are final: they
  *     multiply the unnormalized primitive x^i y^j z^k exp(-alpha r^2); the
  *     library never normalizes.

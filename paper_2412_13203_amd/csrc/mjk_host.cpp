@@ -559,7 +559,7 @@ int mjk_ctx_create(int device, mjk_ctx **out)
     HIP_TRY(hipGetDeviceProperties(&prop, device));
     std::string arch = prop.gcnArchName;
     if (arch.rfind("gfx950", 0) != 0)
-        return fail(MJK_ERR_NO_DEVICE, "mjk_ctx_create: device %d is %s, this build targets gfx950", device,
+        return fail(MJK_ERR_NO_DEVICE, "mjk_ctx_create: device %d is %s, the library targets gfx950", device,
                     arch.c_str());
     char *scr = nullptr;
     {
